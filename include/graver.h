@@ -1,0 +1,205 @@
+/*
+ * graver.h -- C ABI of the MI355X (gfx950) library for parallel Graver-basis
+ * extraction and multi-start augmentation.
+ *
+ * Method: Liu, Wang, Yang, "Parallel Graver Basis Extraction for Nonlinear
+ * Integer Optimization".  The problem (Section 1, eq. INLP) is
+ *     min f(x)  s.t.  A x = b,  l <= x <= u,  x in Z^n,
+ * with A in Z^{m x n}, b in Z^m, l, u in Z^n.
+ *
+ * Conventions for every entry point:
+ *   - Matrices are row-major.  Integer data is int64 unless stated.
+ *   - "device" pointers are HIP device addresses (for example the data
+ *     pointer of a torch tensor on the GPU); "host" pointers are ordinary
+ *     process memory.  Inputs are borrowed for the duration of the call;
+ *     outputs are written by the library into caller-owned buffers.
+ *   - GPU work is issued on the context's stream (graver_ctx_set_stream);
+ *     calls that return a host value synchronise that stream before
+ *     returning.  Each context must be used by one host thread at a time.
+ *   - Every call returns a graver_status.  On an error nothing is written to
+ *     the outputs named as such, and graver_last_error() returns a message.
+ */
+#ifndef GRAVER_H
+#define GRAVER_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GRAVER_OK = 0,
+  GRAVER_E_INVALID = -1,          /* bad shape, pointer or parameter        */
+  GRAVER_E_INFEASIBLE_START = -2, /* augmentation start violates Ax=b or l<=x<=u */
+  GRAVER_E_NOT_KERNEL = -3,       /* a basis column or a candidate has A g != 0 */
+  GRAVER_E_OVERFLOW = -4,         /* exact integer arithmetic would overflow */
+  GRAVER_E_POOL_FULL = -5,        /* more distinct candidates than pool_capacity */
+  GRAVER_E_NOMEM = -6,            /* device allocation failed               */
+  GRAVER_E_DEVICE = -7,           /* HIP runtime error                      */
+  GRAVER_E_CAPACITY = -8          /* caller's output buffer is too small    */
+} graver_status;
+
+typedef enum {
+  GRAVER_FP64 = 0, /* descent in binary64, bit-reproducible (parity mode)   */
+  GRAVER_FP32 = 1, /* descent in binary32 on MFMA                           */
+  GRAVER_BF16 = 2  /* contractions on bf16 MFMA, fp32 accumulate, fp32 polish */
+} graver_precision;
+
+typedef enum {
+  GRAVER_F_QUADRATIC = 1,     /* f(x) = x^T Q x + c^T x, Q symmetric n x n  */
+  GRAVER_F_SEPARABLE_POLY = 2 /* f(x) = sum_i sum_{k=0..deg} coef[i*(deg+1)+k] x_i^k */
+} graver_f_kind;
+
+typedef struct graver_ctx graver_ctx;
+
+/* Instance data, all device pointers.  B is an n x d integer kernel basis
+ * (columns span Ker_Z(A), Theorem 3.2), P = (B^T B)^{-1} B^T is d x n
+ * (Section 3.1) and may be NULL when starts are supplied by the caller. */
+typedef struct {
+  int32_t m, n, d;
+  const int64_t* A; /* m x n */
+  const int64_t* b; /* m, used by graver_augment only */
+  const int64_t* l; /* n */
+  const int64_t* u; /* n */
+  const int64_t* B; /* n x d */
+  const double* P;  /* d x n or NULL */
+} graver_problem;
+
+/* Objective (device pointers).  Q must be symmetric (checked). */
+typedef struct {
+  int32_t kind;       /* graver_f_kind */
+  int32_t degree;     /* separable polynomial degree, 0..8 */
+  const double* Q;    /* n x n (quadratic) */
+  const double* c;    /* n (quadratic) */
+  const double* coef; /* n x (degree+1) (separable polynomial) */
+} graver_objective;
+
+/* Parameters of Parallel Extraction (Algorithm 2, Section 3.2). */
+typedef struct {
+  int64_t n_starts;  /* N, number of parallel starts                        */
+  int32_t iters;     /* T, Adam steps taken by this call                     */
+  int32_t precision; /* graver_precision                                     */
+  double lr, beta1, beta2, eps; /* Adam (paper: lr 0.003; 0.9, 0.999, 1e-8)  */
+  double lambda1, lambda2;      /* eq. loss weights (paper: 0.85, 1)         */
+  int32_t init_mode; /* 0: g ~ Uniform(l-u, u-l) by Philox4x32-10 from seed,
+                        z = P g;  1: z, m, v taken from the state buffers    */
+  int32_t t0;        /* Adam steps already taken (resume); step t0+k uses
+                        bias corrections 1 - beta^(t0+k)                     */
+  int32_t polish_iters; /* GRAVER_BF16: last iterations run in FP32          */
+  int32_t collect;   /* 1: collect candidates (Algorithm 2); 0: descent only */
+  uint64_t seed;     /* Philox key for init_mode 0                           */
+  int64_t first_start; /* Philox counter offset of start 0 (init_mode 0)     */
+  int64_t pool_capacity; /* maximum number of distinct candidates (>= 1)     */
+} graver_extract_params;
+
+/* Optional descent state, device pointers to N x d binary64 arrays.  With
+ * init_mode 1, z (required), m and v (NULL = zeros) are the starting state;
+ * when non-NULL they receive the final state of the call. */
+typedef struct {
+  double* z;
+  double* m;
+  double* v;
+} graver_state;
+
+typedef struct {
+  int64_t start_iterations; /* N * T                                         */
+  int64_t emit_events;      /* iterates whose rounded coordinates changed    */
+  int64_t inbox_events;     /* of those, nonzero and inside [l-u, u-l]       */
+  int64_t unique;           /* distinct candidates collected                 */
+  int64_t verified;         /* distinct candidates with A g = 0              */
+  int64_t out_of_range;     /* iterates with a coordinate beyond the exact range */
+  double ms_init, ms_descent, ms_verify, ms_sort; /* device time per phase  */
+} graver_extract_stats;
+
+typedef struct {
+  int64_t max_steps; /* cap on moves per start (>= 0)                        */
+} graver_augment_params;
+
+/* ---- context ---------------------------------------------------------- */
+
+/* Create a context on HIP device `device`.  The context owns device
+ * workspace (grown on demand, freed by graver_ctx_destroy).  Stream: the
+ * null stream until graver_ctx_set_stream. */
+graver_status graver_ctx_create(graver_ctx** out, int32_t device);
+void graver_ctx_destroy(graver_ctx* ctx);
+/* Issue all GPU work of this context on `hip_stream` (a hipStream_t, e.g.
+ * torch.cuda.current_stream().cuda_stream); NULL selects the null stream. */
+graver_status graver_ctx_set_stream(graver_ctx* ctx, void* hip_stream);
+/* Message of the last error on the calling thread (never NULL). */
+const char* graver_last_error(void);
+const char* graver_status_string(graver_status s);
+
+/* ---- kernel basis (host) ---------------------------------------------- */
+
+/* Lemma 3.1 / Theorem 3.2 and Appendix A.  From A (host, m x n) computes a
+ * unimodular K with A K = (H | 0) in Hermite normal form by integer column
+ * operations, takes B = the last d = n - rank(A) columns, and LLL-reduces
+ * them when `lll` is nonzero (Algorithm 3: size reduction with
+ * nearest-integer coefficients, ties to even, and exchange when
+ * ||b*_{i-1}||^2 > 2 ||b*_i||^2), all in exact integer arithmetic.
+ * Outputs (host): B_out n x d row-major (capacity n*n entries), *d_out,
+ * and when P_out is non-NULL the d x n matrix (B^T B)^{-1} B^T in binary64
+ * (capacity n*n entries).  GRAVER_E_OVERFLOW if an entry of K or B leaves
+ * int64.  Needs no GPU. */
+graver_status graver_kernel_basis(int32_t m, int32_t n, const int64_t* A, int32_t lll,
+                                  int64_t* B_out, int32_t* d_out, double* P_out);
+
+/* ---- the hot path (device) --------------------------------------------- */
+
+/* Parallel Extraction, Algorithm 2 (Section 3.2).  For each of N starts,
+ * T Adam steps on eq. loss
+ *   Phi(z) = ||B z||_1 + lambda1 sum_i (z_i - floor z_i)(ceil z_i - z_i)
+ *            + lambda2 max{1/||z||_inf - 1, 0};
+ * after every step the iterate is rounded to r (nearest integer, ties to
+ * even), g = B r is formed exactly and kept when g != 0 and
+ * l - u <= g <= u - l (condition C4).  Distinct candidates are checked for
+ * A g = 0 (condition C1) and returned sorted lexicographically (signed,
+ * component 0 first) as int8 rows in keys_out (device, capacity keys_cap
+ * rows of n bytes); *count_out (host) receives the count.  Requires
+ * max(u - l) <= 127.  Errors: GRAVER_E_POOL_FULL when more than
+ * pool_capacity distinct candidates appear, GRAVER_E_CAPACITY when
+ * keys_cap is too small, GRAVER_E_NOT_KERNEL when a candidate fails A g = 0.
+ * state and stats may be NULL. */
+graver_status graver_extract(graver_ctx* ctx, const graver_problem* prob,
+                             const graver_extract_params* params, graver_state* state,
+                             int8_t* keys_out, int64_t keys_cap, int64_t* count_out,
+                             graver_extract_stats* stats);
+
+/* Minimality filter with deduplication (condition C3, Section 3; the
+ * conformal order of Section 1).  Input: count_in int8 rows of n bytes
+ * (device).  The set C = X u (-X) without 0 is formed; g in C is dropped
+ * when some h in C, h != g, satisfies h_i g_i >= 0 and |h_i| <= |g_i| for
+ * all i.  Output (device, capacity keys_cap rows): one representative per
+ * pair {g, -g} (first nonzero entry positive), sorted lexicographically;
+ * *count_out (host) receives the count. */
+graver_status graver_filter(graver_ctx* ctx, int32_t n, const int8_t* keys_in, int64_t count_in,
+                            int8_t* keys_out, int64_t keys_cap, int64_t* count_out);
+
+/* Multi-start augmentation (Algorithm 1 from every start; MAPE, Section
+ * 3.3).  Directions: the K int8 rows `dirs` (device) and their negations,
+ * ordered as given with each row followed by its negation.  From each of
+ * the S starts x_starts (device, S x n; each must satisfy A x = b and
+ * l <= x <= u, else GRAVER_E_INFEASIBLE_START) the best move
+ * (g, lambda), lambda = 1..lambda_max(g) keeping x + lambda g in the box,
+ * is the one with the smallest Delta = f(x + lambda g) - f(x) (ties: earlier
+ * direction, then smaller lambda), evaluated in binary64 with a fixed
+ * formula (quadratic: Delta = lambda a_g + lambda^2 q_g with
+ * r = c + 2 Q x, a_g = sum g_i r_i, q_g = sum g_i (sum Q_ij g_j) over the
+ * support of g in ascending order; separable polynomial: the ascending sum
+ * over the support of p_i(x_i + lambda g_i) - p_i(x_i), Horner from the top
+ * coefficient); it is taken when Delta < 0, until no move improves or
+ * max_steps moves were made.  Outputs (device): x_out S x n, f_out S
+ * (f at the end point, ascending sums, no fused multiply-add), steps_out S;
+ * *best_out (host, may be NULL) = index of the smallest f_out (ties: lowest). */
+graver_status graver_augment(graver_ctx* ctx, const graver_problem* prob,
+                             const graver_objective* f, const int8_t* dirs, int64_t K,
+                             int32_t S, const int64_t* x_starts,
+                             const graver_augment_params* params, int64_t* x_out,
+                             double* f_out, int64_t* steps_out, int32_t* best_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GRAVER_H */

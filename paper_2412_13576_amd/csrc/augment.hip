@@ -1,0 +1,329 @@
+// Multi-start augmentation (Algorithm 1 from every start, MAPE Section 3.3)
+// on gfx950.  One step for all active starts is three launches:
+//   prepare : quadratic r = c + 2 Q x per start; separable p_i(x_i) per start
+//   eval    : grid (direction blocks) x (starts); each thread scores one
+//             direction g and its negation over lambda = 1..lambda_max and
+//             the block keeps the best (Delta, position, lambda)
+//   pick    : per start, the best over blocks (a total order, so the result
+//             does not depend on the reduction order); x += lambda g when
+//             Delta < 0, otherwise the start is finished.
+// Every Delta is the fixed binary64 formula of the header with ascending
+// sums over the support of g and no fused multiply-add (this file is
+// compiled with -ffp-contract=off), so moves match a plain evaluation.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <vector>
+
+#include "graver_internal.h"
+
+namespace graver {
+
+struct Move {
+  double delta;
+  uint32_t pos;  // position in D: 2k for row k, 2k+1 for its negation
+  int32_t lam;
+};
+
+__device__ __forceinline__ bool better(const Move& a, const Move& b) {
+  if (a.delta != b.delta) return a.delta < b.delta;
+  if (a.pos != b.pos) return a.pos < b.pos;
+  return a.lam < b.lam;
+}
+
+__global__ void k_check_starts(int n, int m, int S, const int64_t* A, const int64_t* b, const int64_t* l,
+                               const int64_t* u, const int64_t* X, unsigned int* bad) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  const int64_t* x = X + (size_t)s * n;
+  bool ok = true;
+  for (int i = 0; i < n; ++i) ok = ok && x[i] >= l[i] && x[i] <= u[i];
+  for (int r = 0; r < m && ok; ++r) {
+    int64_t acc = 0;
+    for (int j = 0; j < n; ++j) acc += A[(size_t)r * n + j] * x[j];
+    ok = acc == b[r];
+  }
+  if (!ok) atomicAdd(bad, 1u);
+}
+
+__global__ void k_copy_i64(const int64_t* a, int64_t* b, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i];
+}
+__global__ void k_zero_u32(uint32_t* a, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = 0;
+}
+__global__ void k_zero_i64(int64_t* a, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = 0;
+}
+
+// q_g = sum_{i in supp} g_i * (sum_{j in supp} Q_ij g_j), ascending.
+__global__ void k_qg(int n, int K, const int8_t* __restrict__ F, const double* __restrict__ Q, double* qg) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  const int8_t* g = F + (size_t)k * n;
+  double q = 0.0;
+  for (int i = 0; i < n; ++i) {
+    if (g[i] == 0) continue;
+    double t = 0.0;
+    for (int j = 0; j < n; ++j) {
+      if (g[j] == 0) continue;
+      t = t + Q[(size_t)i * n + j] * (double)g[j];
+    }
+    q = q + (double)g[i] * t;
+  }
+  qg[k] = q;
+}
+
+// tab[i * w + (v - l_i)] = p_i(v) by Horner from the top coefficient.
+__global__ void k_poly_table(int n, int deg, int w, const double* coef, const int64_t* l, const int64_t* u,
+                             double* tab) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * w) return;
+  int i = t / w, o = t % w;
+  int64_t v = l[i] + o;
+  if (v > u[i]) return;
+  const double* c = coef + (size_t)i * (deg + 1);
+  double x = (double)v;
+  double p = c[deg];
+  for (int k = deg - 1; k >= 0; --k) p = p * x + c[k];
+  tab[t] = p;
+}
+
+// quadratic: r[s, i] = c_i + 2 * (sum_j Q_ij x_j); separable: px[s, i] = p_i(x_i).
+__global__ void k_prepare(AugArgs a, const int64_t* X, const uint32_t* done, const double* tab, int w,
+                          double* R) {
+  int s = blockIdx.y;
+  if (done[s]) return;
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const int64_t* x = X + (size_t)s * a.n;
+  if (a.kind == GRAVER_F_QUADRATIC) {
+    double acc = 0.0;
+    for (int j = 0; j < a.n; ++j) acc = acc + a.Q[(size_t)i * a.n + j] * (double)x[j];
+    R[(size_t)s * a.n + i] = a.c[i] + 2.0 * acc;
+  } else {
+    R[(size_t)s * a.n + i] = tab[(size_t)i * w + (x[i] - a.l[i])];
+  }
+}
+
+constexpr int kEvalThreads = 256;
+
+__global__ void k_eval(AugArgs a, const int64_t* X, const uint32_t* done, const double* R, const double* qg,
+                       const double* tab, int w, Move* partial) {
+  const int s = blockIdx.y;
+  if (done[s]) return;
+  const int n = a.n;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t* x = X + (size_t)s * n;
+  const double* r = R + (size_t)s * n;
+  Move best{INFINITY, 0xFFFFFFFFu, 0};
+  if (k < a.K) {
+    const int8_t* g = a.dirs + (size_t)k * n;
+    // lambda_max for +g and -g
+    int64_t lp = INT64_MAX, ln = INT64_MAX;
+    bool any = false;
+    for (int i = 0; i < n; ++i) {
+      int gi = g[i];
+      if (gi == 0) continue;
+      any = true;
+      int64_t up = a.u[i] - x[i], dn = x[i] - a.l[i];
+      if (gi > 0) {
+        lp = min(lp, up / gi);
+        ln = min(ln, dn / gi);
+      } else {
+        lp = min(lp, dn / (-gi));
+        ln = min(ln, up / (-gi));
+      }
+    }
+    if (any) {
+      if (a.kind == GRAVER_F_QUADRATIC) {
+        double ag = 0.0;
+        for (int i = 0; i < n; ++i) {
+          int gi = g[i];
+          if (gi != 0) ag = ag + (double)gi * r[i];
+        }
+        const double q = qg[k];
+        for (int sg = 0; sg < 2; ++sg) {
+          const int64_t lm = sg ? ln : lp;
+          const double av = sg ? -ag : ag;
+          for (int64_t lam = 1; lam <= lm; ++lam) {
+            double lf = (double)lam;
+            Move mv{(lf * av) + ((lf * lf) * q), (uint32_t)(2 * k + sg), (int32_t)lam};
+            if (better(mv, best)) best = mv;
+          }
+        }
+      } else {
+        for (int sg = 0; sg < 2; ++sg) {
+          const int64_t lm = sg ? ln : lp;
+          const int sgn = sg ? -1 : 1;
+          for (int64_t lam = 1; lam <= lm; ++lam) {
+            double acc = 0.0;
+            for (int i = 0; i < n; ++i) {
+              int gi = g[i];
+              if (gi == 0) continue;
+              int64_t v = x[i] + lam * sgn * gi;
+              acc = acc + (tab[(size_t)i * w + (v - a.l[i])] - r[i]);
+            }
+            Move mv{acc, (uint32_t)(2 * k + sg), (int32_t)lam};
+            if (better(mv, best)) best = mv;
+          }
+        }
+      }
+    }
+  }
+  __shared__ Move sh[kEvalThreads];
+  sh[threadIdx.x] = best;
+  __syncthreads();
+  for (int o = kEvalThreads / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o && better(sh[threadIdx.x + o], sh[threadIdx.x])) sh[threadIdx.x] = sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[(size_t)s * gridDim.x + blockIdx.x] = sh[0];
+}
+
+__global__ void k_pick(AugArgs a, int nblk, const Move* partial, int64_t* X, uint32_t* done, int64_t* steps,
+                       uint32_t* active) {
+  const int s = blockIdx.x;
+  if (done[s]) return;
+  __shared__ Move sh[256];
+  Move best{INFINITY, 0xFFFFFFFFu, 0};
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+    Move mv = partial[(size_t)s * nblk + b];
+    if (better(mv, best)) best = mv;
+  }
+  sh[threadIdx.x] = best;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o && better(sh[threadIdx.x + o], sh[threadIdx.x])) sh[threadIdx.x] = sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  best = sh[0];
+  const bool take = best.pos != 0xFFFFFFFFu && best.delta < 0.0 && steps[s] < a.max_steps;
+  if (!take) {
+    if (threadIdx.x == 0) done[s] = 1;
+    return;
+  }
+  const int k = (int)(best.pos / 2);
+  const int64_t mult = (best.pos & 1) ? -(int64_t)best.lam : (int64_t)best.lam;
+  const int8_t* g = a.dirs + (size_t)k * a.n;
+  for (int i = threadIdx.x; i < a.n; i += blockDim.x) X[(size_t)s * a.n + i] += mult * (int64_t)g[i];
+  if (threadIdx.x == 0) {
+    steps[s] += 1;
+    atomicOr(active, 1u);
+  }
+}
+
+// f(x) with ascending sums and separate rounding: quadratic
+// (sum_i x_i * (sum_j Q_ij x_j)) + (sum_i c_i x_i); separable sum_i p_i(x_i).
+__global__ void k_fval(AugArgs a, const int64_t* X, double* T, double* fout) {
+  const int s = blockIdx.x;
+  const int n = a.n;
+  const int64_t* x = X + (size_t)s * n;
+  double* t = T + (size_t)s * n;
+  if (a.kind == GRAVER_F_QUADRATIC) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      double acc = 0.0;
+      for (int j = 0; j < n; ++j) acc = acc + a.Q[(size_t)i * n + j] * (double)x[j];
+      t[i] = acc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double s1 = 0.0, s2 = 0.0;
+      for (int i = 0; i < n; ++i) s1 = s1 + (double)x[i] * t[i];
+      for (int i = 0; i < n; ++i) s2 = s2 + a.c[i] * (double)x[i];
+      fout[s] = s1 + s2;
+    }
+  } else if (threadIdx.x == 0) {
+    double acc = 0.0;
+    for (int i = 0; i < n; ++i) {
+      const double* c = a.coef + (size_t)i * (a.degree + 1);
+      double xv = (double)x[i];
+      double p = c[a.degree];
+      for (int k = a.degree - 1; k >= 0; --k) p = p * xv + c[k];
+      acc = acc + p;
+    }
+    fout[s] = acc;
+  }
+}
+
+__global__ void k_best(int S, const double* f, int32_t* best) {
+  if (threadIdx.x != 0) return;
+  int b = 0;
+  for (int s = 1; s < S; ++s)
+    if (f[s] < f[b]) b = s;
+  *best = b;
+}
+
+graver_status run_augment(graver_ctx* ctx, const AugArgs& a, const int64_t* x_starts, int64_t* x_out,
+                          double* f_out, int64_t* steps_out, int32_t* best_out) {
+  hipStream_t s = ctx->stream;
+  graver_status st = GRAVER_OK;
+  const int n = a.n, S = a.S, K = a.K;
+  unsigned int* bad = (unsigned int*)ws_get(ctx, WS_FLAGS, 64, &st);
+  uint32_t* done = (uint32_t*)ws_get(ctx, WS_A_DONE, (size_t)S * 4 + 64, &st);
+  double* R = (double*)ws_get(ctx, WS_A_R, (size_t)S * n * 8, &st);
+  const int nblk = K > 0 ? (K + kEvalThreads - 1) / kEvalThreads : 1;
+  Move* partial = (Move*)ws_get(ctx, WS_A_PART, (size_t)S * nblk * sizeof(Move), &st);
+  double* qg = (double*)ws_get(ctx, WS_A_QG, (size_t)(K > 0 ? K : 1) * 8, &st);
+  int32_t* dbest = (int32_t*)ws_get(ctx, WS_MISC, 64, &st);
+  if (!bad || !done || !R || !partial || !qg || !dbest) return st;
+
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, bad, (size_t)16);
+  hipLaunchKernelGGL(k_check_starts, dim3((S + 63) / 64), dim3(64), 0, s, n, a.m, S, a.A, a.b, a.l, a.u,
+                     x_starts, bad);
+  unsigned int hbad = 0;
+  hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, s);
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_error(e, "augment start check");
+  if (hbad) return set_error(GRAVER_E_INFEASIBLE_START, "a start violates A x = b or l <= x <= u");
+
+  // value table for separable objectives (width = max(u - l) + 1)
+  int w = 1;
+  double* tab = nullptr;
+  if (a.kind == GRAVER_F_SEPARABLE_POLY) {
+    std::vector<int64_t> hl(n), hu(n);
+    hipMemcpyAsync(hl.data(), a.l, n * 8, hipMemcpyDeviceToHost, s);
+    hipMemcpyAsync(hu.data(), a.u, n * 8, hipMemcpyDeviceToHost, s);
+    hipStreamSynchronize(s);
+    for (int i = 0; i < n; ++i) w = (int)std::max<int64_t>(w, hu[i] - hl[i] + 1);
+    tab = (double*)ws_get(ctx, WS_A_TAB, (size_t)n * w * 8, &st);
+    if (!tab) return st;
+    hipLaunchKernelGGL(k_poly_table, dim3((n * w + 255) / 256), dim3(256), 0, s, n, a.degree, w, a.coef, a.l,
+                       a.u, tab);
+  }
+  size_t sn = (size_t)S * n;
+  hipLaunchKernelGGL(k_copy_i64, dim3((unsigned)((sn + 255) / 256)), dim3(256), 0, s, x_starts, x_out, sn);
+  hipLaunchKernelGGL(k_zero_u32, dim3((S + 255) / 256), dim3(256), 0, s, done, (size_t)S);
+  hipLaunchKernelGGL(k_zero_i64, dim3((S + 255) / 256), dim3(256), 0, s, steps_out, (size_t)S);
+  if (K > 0 && a.kind == GRAVER_F_QUADRATIC)
+    hipLaunchKernelGGL(k_qg, dim3((K + 255) / 256), dim3(256), 0, s, n, K, a.dirs, a.Q, qg);
+
+  uint32_t* active = bad + 4;
+  if (K > 0) {
+    for (int64_t step = 0;; ++step) {
+      hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, active, (size_t)1);
+      hipLaunchKernelGGL(k_prepare, dim3((n + 127) / 128, S), dim3(128), 0, s, a, x_out, done, tab, w, R);
+      hipLaunchKernelGGL(k_eval, dim3(nblk, S), dim3(kEvalThreads), 0, s, a, x_out, done, R, qg, tab, w,
+                         partial);
+      hipLaunchKernelGGL(k_pick, dim3(S), dim3(256), 0, s, a, nblk, partial, x_out, done, steps_out, active);
+      uint32_t hact = 0;
+      hipMemcpyAsync(&hact, active, 4, hipMemcpyDeviceToHost, s);
+      e = hipStreamSynchronize(s);
+      if (e != hipSuccess) return hip_error(e, "augment step");
+      if (!hact) break;
+    }
+  }
+  hipLaunchKernelGGL(k_fval, dim3(S), dim3(256), 0, s, a, x_out, R, f_out);
+  hipLaunchKernelGGL(k_best, dim3(1), dim3(64), 0, s, S, f_out, dbest);
+  int32_t hb = 0;
+  hipMemcpyAsync(&hb, dbest, 4, hipMemcpyDeviceToHost, s);
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_error(e, "augment objective");
+  if (best_out) *best_out = hb;
+  return GRAVER_OK;
+}
+
+}  // namespace graver

@@ -1,0 +1,113 @@
+// Internal declarations shared by the host entry points and the kernel
+// launchers of the gfx950 library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "graver.h"
+
+struct graver_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  static constexpr int kSlots = 40;
+  void* buf[kSlots] = {};
+  size_t cap[kSlots] = {};
+  void* host_pinned = nullptr;  // small pinned staging area
+  size_t host_pinned_cap = 0;
+};
+
+namespace graver {
+
+graver_status set_error(graver_status s, const std::string& msg);
+graver_status hip_error(hipError_t e, const char* what);
+
+// Workspace slots (each grows on demand and is reused across calls).
+enum Slot : int {
+  WS_Z = 0, WS_M, WS_V, WS_RPREV, WS_SIGN, WS_KEYSCRATCH, WS_G0,
+  WS_POOL_KEYS, WS_POOL_TABLE, WS_POOL_COUNT, WS_COUNTERS,
+  WS_BF, WS_BC, WS_SORT_IDX, WS_SORT_TMP, WS_FLAGS, WS_SCAN, WS_SCAN2,
+  WS_F_CANON, WS_F_UNIQ, WS_F_L1, WS_F_MASK, WS_F_LO, WS_F_ALIVE, WS_F_OUT,
+  WS_A_R, WS_A_PART, WS_A_DONE, WS_A_QG, WS_A_TAB, WS_A_PX, WS_A_STEPS,
+  WS_MF_B, WS_MF_BT, WS_MF_STATE, WS_MISC,
+};
+void* ws_get(graver_ctx* ctx, int slot, size_t bytes, graver_status* st);
+
+graver_status kernel_basis_host(int32_t m, int32_t n, const int64_t* A, int32_t do_lll,
+                                int64_t* B_out, int32_t* d_out, double* P_out);
+
+// ---- device pool (hash set of int8 keys) --------------------------------
+struct PoolDev {
+  int8_t* keys;        // cap x stride bytes
+  uint64_t* table;     // tsize entries, 0 = empty
+  uint32_t* count;     // [0] allocated keys, [1] full flag, [2] probe-limit flag
+  uint64_t tmask;      // tsize - 1
+  uint32_t cap;
+  int32_t n, stride;   // key length, row stride (multiple of 16)
+};
+inline int key_stride(int n) { return (n + 15) / 16 * 16; }
+
+// Counters written by the descent kernels (atomic adds, int64).
+enum Counter : int { C_EMIT = 0, C_INBOX, C_RANGE, C_NCOUNTERS };
+
+// ---- launchers (implemented in the .hip files) --------------------------
+struct DescentArgs {
+  int32_t n, d, N, T;
+  const int64_t* B;     // n x d (device)
+  const int64_t* l;
+  const int64_t* u;
+  double lr, beta1, beta2, eps, lambda1, lambda2;
+  double one_minus_b1, one_minus_b2;
+  const double* bc;     // 2*T bias corrections (device): [2k] = 1-b1^t, [2k+1] = 1-b2^t
+  int32_t collect;
+};
+
+hipError_t launch_init_box(hipStream_t s, int n, int d, int64_t N, const double* P,
+                           const int64_t* l, const int64_t* u, uint64_t seed,
+                           int64_t first_start, double* g_scratch, double* z_out);
+hipError_t launch_descent_fp64(hipStream_t s, const DescentArgs& a, double* z, double* m,
+                               double* v, double* rprev, int8_t* sign_scratch,
+                               int8_t* key_scratch, PoolDev pool, unsigned long long* counters);
+bool descent_f32_supported(int n, int d);
+hipError_t launch_descent_f32(hipStream_t s, const DescentArgs& a, const float* Bf_packed,
+                              const float* BTf_packed, float* state, PoolDev pool,
+                              unsigned long long* counters, float zrange);
+hipError_t launch_f32_pack(hipStream_t s, int n, int d, const int64_t* B, float* Bp, float* BTp,
+                           int* rowl1max_dev);
+size_t f32_pack_floats(int n, int d);
+size_t f32_state_floats(int n, int d, int64_t N);
+hipError_t launch_f32_state_io(hipStream_t s, int n, int d, int64_t N, float* state,
+                               double* z, double* m, double* v, int to_device);
+
+hipError_t launch_pool_clear(hipStream_t s, PoolDev p);
+hipError_t launch_verify(hipStream_t s, PoolDev p, uint32_t count, int m, const int64_t* A,
+                         unsigned int* bad);
+hipError_t launch_sort_keys(hipStream_t s, const int8_t* keys, int stride, int n, uint32_t count,
+                            uint32_t* idx, uint32_t* tmp, int by_l1, const int32_t* l1);
+hipError_t launch_gather_keys(hipStream_t s, const int8_t* keys, int stride, int n,
+                              const uint32_t* idx, uint32_t count, int8_t* out, int out_stride);
+
+// filter
+hipError_t launch_filter(hipStream_t s, graver_ctx* ctx, int n, const int8_t* in, int64_t count_in,
+                         int8_t* out, int64_t cap, int64_t* count_out, graver_status* st);
+
+// augment
+struct AugArgs {
+  int32_t n, m, S, K;
+  const int64_t* A;
+  const int64_t* b;
+  const int64_t* l;
+  const int64_t* u;
+  int32_t kind, degree;
+  const double* Q;
+  const double* c;
+  const double* coef;
+  const int8_t* dirs;
+  int64_t max_steps;
+};
+graver_status run_augment(graver_ctx* ctx, const AugArgs& a, const int64_t* x_starts,
+                          int64_t* x_out, double* f_out, int64_t* steps_out, int32_t* best_out);
+
+}  // namespace graver

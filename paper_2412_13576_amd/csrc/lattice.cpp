@@ -1,0 +1,250 @@
+// Host-side integer kernel basis of A (Section 3.1 of the paper):
+//  * column-style Hermite normal form A K = (H | 0) with K unimodular
+//    (Lemma 3.1); B = last n - rank(A) columns of K spans Ker_Z(A)
+//    (Theorem 3.2);
+//  * LLL reduction (Appendix A, Algorithm 3) in exact integer arithmetic
+//    using the integral Gram-Schmidt quantities d_k (Gram determinants) and
+//    lambda_ij = d_j mu_ij (Cohen, "A Course in Computational Algebraic
+//    Number Theory", Sec. 2.6);
+//  * the coordinate map P = (B^T B)^{-1} B^T (Section 3.1) in binary64.
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "bigint.h"
+#include "graver_internal.h"
+
+namespace graver {
+namespace {
+
+struct Overflow {};
+
+inline int64_t chk_mul(int64_t a, int64_t b) {
+  int64_t r;
+  if (__builtin_mul_overflow(a, b, &r)) throw Overflow();
+  return r;
+}
+inline int64_t chk_sub(int64_t a, int64_t b) {
+  int64_t r;
+  if (__builtin_sub_overflow(a, b, &r)) throw Overflow();
+  return r;
+}
+inline int64_t floor_div(int64_t a, int64_t b) {
+  int64_t q = a / b, r = a % b;
+  if (r != 0 && ((r < 0) != (b < 0))) --q;
+  return q;
+}
+
+// Columns are stored contiguously: col[c][row].
+struct ColMat {
+  int rows, cols;
+  std::vector<int64_t> v;
+  ColMat(int r, int c) : rows(r), cols(c), v((size_t)r * c, 0) {}
+  int64_t& at(int r, int c) { return v[(size_t)c * rows + r]; }
+  int64_t* col(int c) { return &v[(size_t)c * rows]; }
+};
+
+// Hermite normal form by unimodular column operations.  Row i: among the
+// columns p..n-1 pick the nonzero entry of smallest magnitude (ties: lowest
+// column), move it to column p, reduce every other column k > p by
+// floor(w_ik / w_ip) times column p; repeat until column p is the only
+// nonzero among p..n-1.  Make the pivot positive, reduce entries left of
+// it into [0, pivot), advance p.  Rows without a nonzero in p..n-1 are
+// dependent and give no pivot.  Returns the rank; K is n x n.
+int hnf(int m, int n, const int64_t* A, ColMat& K) {
+  ColMat W(m, n);
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < n; ++j) W.at(i, j) = A[(size_t)i * n + j];
+  for (int i = 0; i < n; ++i) K.at(i, i) = 1;
+  auto axpy = [&](int dst, int src, int64_t q) {  // col dst -= q col src
+    int64_t *wd = W.col(dst), *ws = W.col(src), *kd = K.col(dst), *ks = K.col(src);
+    for (int r = 0; r < m; ++r) wd[r] = chk_sub(wd[r], chk_mul(q, ws[r]));
+    for (int r = 0; r < n; ++r) kd[r] = chk_sub(kd[r], chk_mul(q, ks[r]));
+  };
+  auto swapc = [&](int a, int b) {
+    for (int r = 0; r < m; ++r) std::swap(W.at(r, a), W.at(r, b));
+    for (int r = 0; r < n; ++r) std::swap(K.at(r, a), K.at(r, b));
+  };
+  int p = 0;
+  for (int i = 0; i < m && p < n; ++i) {
+    bool pivoted = false;
+    for (;;) {
+      int piv = -1;
+      int64_t best = 0;
+      for (int k = p; k < n; ++k) {
+        int64_t w = W.at(i, k);
+        if (w == 0) continue;
+        if (w == INT64_MIN) throw Overflow();
+        int64_t a = w < 0 ? -w : w;
+        if (piv < 0 || a < best) {
+          piv = k;
+          best = a;
+        }
+      }
+      if (piv < 0) break;
+      if (piv != p) swapc(p, piv);
+      pivoted = true;
+      bool clean = true;
+      for (int k = p + 1; k < n; ++k) {
+        if (W.at(i, k) != 0) {
+          int64_t q = floor_div(W.at(i, k), W.at(i, p));
+          axpy(k, p, q);
+          if (W.at(i, k) != 0) clean = false;
+        }
+      }
+      if (clean) break;
+    }
+    if (!pivoted) continue;
+    if (W.at(i, p) < 0) {
+      for (int r = 0; r < m; ++r) W.at(r, p) = chk_sub(0, W.at(r, p));
+      for (int r = 0; r < n; ++r) K.at(r, p) = chk_sub(0, K.at(r, p));
+    }
+    for (int j = 0; j < p; ++j) {
+      int64_t q = floor_div(W.at(i, j), W.at(i, p));
+      if (q != 0) axpy(j, p, q);
+    }
+    ++p;
+  }
+  return p;
+}
+
+// LLL in the paper's order (Appendix A, Algorithm 3): with i from the
+// second vector, size-reduce b_i against b_{i-1}, ..., b_1, then exchange
+// b_i, b_{i-1} when ||b*_{i-1}||^2 > 2 ||b*_i||^2 (i.e. D[i]^2 > 2 D[i+1]
+// D[i-1]) and step back (not below the second vector), else advance.
+// b: d vectors of length n (int64, overflow-checked).
+void lll(int n, int d, std::vector<std::vector<int64_t>>& b) {
+  if (d <= 1) return;
+  std::vector<BigInt> D(d + 1);
+  std::vector<std::vector<BigInt>> lam(d, std::vector<BigInt>(d));
+  D[0] = BigInt(1);
+  auto dot = [&](int a, int c) {
+    __int128 s = 0;
+    for (int r = 0; r < n; ++r) s += (__int128)b[a][r] * b[c][r];
+    return BigInt::from_i128(s);
+  };
+  for (int k = 0; k < d; ++k) {
+    for (int j = 0; j <= k; ++j) {
+      BigInt u = dot(k, j);
+      for (int i = 0; i < j; ++i) u = BigInt::div_exact(D[i + 1] * u - lam[k][i] * lam[j][i], D[i]);
+      if (j < k) {
+        lam[k][j] = u;
+      } else {
+        if (u.is_zero()) throw std::logic_error("kernel basis columns are dependent");
+        D[k + 1] = u;
+      }
+    }
+  }
+  auto size_reduce = [&](int k, int j) {
+    BigInt q = BigInt::div_round_half_even(lam[k][j], D[j + 1]);
+    if (q.is_zero()) return;
+    if (!q.fits_i64()) throw Overflow();
+    int64_t qi = q.to_i64();
+    for (int r = 0; r < n; ++r) b[k][r] = chk_sub(b[k][r], chk_mul(qi, b[j][r]));
+    lam[k][j] = lam[k][j] - q * D[j + 1];
+    for (int i = 0; i < j; ++i) lam[k][i] = lam[k][i] - q * lam[j][i];
+  };
+  auto exchange = [&](int k) {
+    std::swap(b[k], b[k - 1]);
+    for (int j = 0; j < k - 1; ++j) std::swap(lam[k][j], lam[k - 1][j]);
+    BigInt lk = lam[k][k - 1];
+    BigInt Bn = BigInt::div_exact(D[k - 1] * D[k + 1] + lk * lk, D[k]);
+    for (int i = k + 1; i < d; ++i) {
+      BigInt t = lam[i][k];
+      lam[i][k] = BigInt::div_exact(D[k + 1] * lam[i][k - 1] - lk * t, D[k]);
+      lam[i][k - 1] = BigInt::div_exact(Bn * t + lk * lam[i][k], D[k + 1]);
+    }
+    D[k] = Bn;
+  };
+  int i = 1;
+  const BigInt two(2);
+  while (i < d) {
+    for (int j = i - 1; j >= 0; --j) size_reduce(i, j);
+    if (D[i] * D[i] > two * D[i + 1] * D[i - 1]) {
+      exchange(i);
+      i = i - 1 > 1 ? i - 1 : 1;
+    } else {
+      ++i;
+    }
+  }
+}
+
+// P = (B^T B)^{-1} B^T by Cholesky with one step of iterative refinement.
+void projector(int n, int d, const std::vector<std::vector<int64_t>>& b, double* P) {
+  std::vector<double> G((size_t)d * d), L((size_t)d * d, 0.0);
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j) {
+      __int128 s = 0;
+      for (int r = 0; r < n; ++r) s += (__int128)b[i][r] * b[j][r];
+      G[(size_t)i * d + j] = (double)s;
+    }
+  for (int j = 0; j < d; ++j) {
+    long double s = G[(size_t)j * d + j];
+    for (int k = 0; k < j; ++k) s -= (long double)L[(size_t)j * d + k] * L[(size_t)j * d + k];
+    double dj = std::sqrt((double)s);
+    L[(size_t)j * d + j] = dj;
+    for (int i = j + 1; i < d; ++i) {
+      long double t = G[(size_t)i * d + j];
+      for (int k = 0; k < j; ++k) t -= (long double)L[(size_t)i * d + k] * L[(size_t)j * d + k];
+      L[(size_t)i * d + j] = (double)(t / dj);
+    }
+  }
+  auto solve = [&](std::vector<long double>& x) {  // G x = rhs in place
+    for (int i = 0; i < d; ++i) {
+      long double s = x[i];
+      for (int k = 0; k < i; ++k) s -= (long double)L[(size_t)i * d + k] * x[k];
+      x[i] = s / L[(size_t)i * d + i];
+    }
+    for (int i = d - 1; i >= 0; --i) {
+      long double s = x[i];
+      for (int k = i + 1; k < d; ++k) s -= (long double)L[(size_t)k * d + i] * x[k];
+      x[i] = s / L[(size_t)i * d + i];
+    }
+  };
+  std::vector<long double> x(d), res(d);
+  for (int r = 0; r < n; ++r) {
+    for (int i = 0; i < d; ++i) x[i] = (long double)b[i][r];
+    solve(x);
+    for (int i = 0; i < d; ++i) {
+      long double s = (long double)b[i][r];
+      for (int k = 0; k < d; ++k) s -= (long double)G[(size_t)i * d + k] * x[k];
+      res[i] = s;
+    }
+    solve(res);
+    for (int i = 0; i < d; ++i) P[(size_t)i * n + r] = (double)(x[i] + res[i]);
+  }
+}
+
+}  // namespace
+
+graver_status kernel_basis_host(int32_t m, int32_t n, const int64_t* A, int32_t do_lll,
+                                int64_t* B_out, int32_t* d_out, double* P_out) {
+  try {
+    ColMat K(n, n);
+    int r = hnf(m, n, A, K);
+    int d = n - r;
+    std::vector<std::vector<int64_t>> b(d, std::vector<int64_t>(n));
+    for (int c = 0; c < d; ++c)
+      for (int row = 0; row < n; ++row) b[c][row] = K.at(row, r + c);
+    if (do_lll) lll(n, d, b);
+    // exact check A B = 0 (Theorem 3.2 relies on it)
+    for (int i = 0; i < m; ++i)
+      for (int c = 0; c < d; ++c) {
+        __int128 s = 0;
+        for (int j = 0; j < n; ++j) s += (__int128)A[(size_t)i * n + j] * b[c][j];
+        if (s != 0) return set_error(GRAVER_E_NOT_KERNEL, "computed basis is not in Ker(A)");
+      }
+    for (int row = 0; row < n; ++row)
+      for (int c = 0; c < d; ++c) B_out[(size_t)row * d + c] = b[c][row];
+    *d_out = d;
+    if (P_out && d > 0) projector(n, d, b, P_out);
+    return GRAVER_OK;
+  } catch (const Overflow&) {
+    return set_error(GRAVER_E_OVERFLOW, "int64 overflow in the kernel basis computation");
+  } catch (const std::exception& e) {
+    return set_error(GRAVER_E_INVALID, std::string("kernel basis: ") + e.what());
+  }
+}
+
+}  // namespace graver

@@ -1,0 +1,248 @@
+"""ctypes binding of the gfx950 C-ABI library (libgraver.so).
+
+Argument marshalling only: every stage of the path runs in the library's
+HIP kernels.  PyTorch provides device memory and the stream.  The names
+mirror include/graver.h.  Loading fails loudly when the library has not
+been built; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgraver.so")
+
+GRAVER_FP64, GRAVER_FP32, GRAVER_BF16 = 0, 1, 2
+GRAVER_F_QUADRATIC, GRAVER_F_SEPARABLE_POLY = 1, 2
+STATUS = {0: "OK", -1: "E_INVALID", -2: "E_INFEASIBLE_START", -3: "E_NOT_KERNEL",
+          -4: "E_OVERFLOW", -5: "E_POOL_FULL", -6: "E_NOMEM", -7: "E_DEVICE", -8: "E_CAPACITY"}
+
+EXPORTED = ["graver_ctx_create", "graver_ctx_destroy", "graver_ctx_set_stream", "graver_last_error",
+            "graver_status_string", "graver_kernel_basis", "graver_extract", "graver_filter",
+            "graver_augment"]
+
+
+class GraverError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Problem(C.Structure):
+    _fields_ = [("m", C.c_int32), ("n", C.c_int32), ("d", C.c_int32),
+                ("A", C.c_void_p), ("b", C.c_void_p), ("l", C.c_void_p), ("u", C.c_void_p),
+                ("B", C.c_void_p), ("P", C.c_void_p)]
+
+
+class ObjectiveC(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("degree", C.c_int32), ("Q", C.c_void_p), ("c", C.c_void_p),
+                ("coef", C.c_void_p)]
+
+
+class ExtractParams(C.Structure):
+    _fields_ = [("n_starts", C.c_int64), ("iters", C.c_int32), ("precision", C.c_int32),
+                ("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
+                ("lambda1", C.c_double), ("lambda2", C.c_double),
+                ("init_mode", C.c_int32), ("t0", C.c_int32), ("polish_iters", C.c_int32),
+                ("collect", C.c_int32), ("seed", C.c_uint64), ("first_start", C.c_int64),
+                ("pool_capacity", C.c_int64)]
+
+
+class State(C.Structure):
+    _fields_ = [("z", C.c_void_p), ("m", C.c_void_p), ("v", C.c_void_p)]
+
+
+class ExtractStats(C.Structure):
+    _fields_ = [("start_iterations", C.c_int64), ("emit_events", C.c_int64),
+                ("inbox_events", C.c_int64), ("unique", C.c_int64), ("verified", C.c_int64),
+                ("out_of_range", C.c_int64), ("ms_init", C.c_double), ("ms_descent", C.c_double),
+                ("ms_verify", C.c_double), ("ms_sort", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class AugmentParams(C.Structure):
+    _fields_ = [("max_steps", C.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (import torch first so the HIP runtime is shared)."""
+    global _lib
+    if _lib is None:
+        import torch  # noqa: F401  (loads the HIP runtime the library binds to)
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+        L = C.CDLL(LIB_PATH)
+        L.graver_ctx_create.argtypes = [C.POINTER(C.c_void_p), C.c_int32]
+        L.graver_ctx_destroy.argtypes = [C.c_void_p]
+        L.graver_ctx_destroy.restype = None
+        L.graver_ctx_set_stream.argtypes = [C.c_void_p, C.c_void_p]
+        L.graver_last_error.restype = C.c_char_p
+        L.graver_status_string.argtypes = [C.c_int]
+        L.graver_status_string.restype = C.c_char_p
+        L.graver_kernel_basis.argtypes = [C.c_int32, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p,
+                                          C.POINTER(C.c_int32), C.c_void_p]
+        L.graver_extract.argtypes = [C.c_void_p, C.POINTER(Problem), C.POINTER(ExtractParams),
+                                     C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(C.c_int64),
+                                     C.c_void_p]
+        L.graver_filter.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p,
+                                    C.c_int64, C.POINTER(C.c_int64)]
+        L.graver_augment.argtypes = [C.c_void_p, C.POINTER(Problem), C.POINTER(ObjectiveC), C.c_void_p,
+                                     C.c_int64, C.c_int32, C.c_void_p, C.POINTER(AugmentParams),
+                                     C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]
+        for name in ("graver_ctx_create", "graver_ctx_set_stream", "graver_kernel_basis",
+                     "graver_extract", "graver_filter", "graver_augment"):
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise GraverError(status, lib().graver_last_error().decode())
+
+
+def kernel_basis(A: np.ndarray, lll: bool = True):
+    """B (n x d int64) and P = (B^T B)^-1 B^T (d x n float64), computed on the host."""
+    A = np.ascontiguousarray(A, dtype=np.int64)
+    m, n = A.shape
+    Bbuf = np.zeros(n * n, np.int64)
+    Pbuf = np.zeros(n * n, np.float64)
+    d = C.c_int32(0)
+    _check(lib().graver_kernel_basis(m, n, A.ctypes.data, int(lll), Bbuf.ctypes.data, C.byref(d),
+                                     Pbuf.ctypes.data))
+    d = d.value
+    return Bbuf[: n * d].reshape(n, d).copy(), Pbuf[: d * n].reshape(d, n).copy()
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+class Context:
+    """A library context bound to a device and torch's current stream."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        h = C.c_void_p()
+        _check(lib().graver_ctx_create(C.byref(h), device))
+        self.h = h
+        self.device = device
+        self.set_stream(torch.cuda.current_stream(device))
+
+    def set_stream(self, stream):
+        _check(lib().graver_ctx_set_stream(self.h, C.c_void_p(stream.cuda_stream)))
+
+    def close(self):
+        if self.h:
+            lib().graver_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class DeviceProblem:
+    """Device-resident instance tensors (torch, on the GPU)."""
+    A: "object"
+    b: "object"
+    l: "object"
+    u: "object"
+    B: "object"
+    P: "object" = None
+
+    @staticmethod
+    def from_numpy(A, b, l, u, B, P=None, device="cuda"):
+        import torch
+        t = lambda x, dt: None if x is None else torch.as_tensor(np.ascontiguousarray(x), dtype=dt, device=device)
+        return DeviceProblem(t(A, torch.int64), t(b, torch.int64), t(l, torch.int64), t(u, torch.int64),
+                             t(B, torch.int64), t(P, torch.float64))
+
+    def c(self) -> Problem:
+        m, n = self.A.shape
+        d = self.B.shape[1]
+        return Problem(m, n, d, _ptr(self.A), _ptr(self.b), _ptr(self.l), _ptr(self.u), _ptr(self.B),
+                       _ptr(self.P))
+
+
+def extract_params(n_starts, iters, precision=GRAVER_FP64, init_mode=0, seed=0, t0=0,
+                   pool_capacity=1 << 20, collect=1, lr=0.003, beta1=0.9, beta2=0.999, eps=1e-8,
+                   lambda1=0.85, lambda2=1.0, polish_iters=0, first_start=0) -> ExtractParams:
+    return ExtractParams(n_starts, iters, precision, lr, beta1, beta2, eps, lambda1, lambda2, init_mode,
+                         t0, polish_iters, collect, seed, first_start, pool_capacity)
+
+
+def extract(ctx: Context, prob: DeviceProblem, params: ExtractParams, state=None, keys_cap=None):
+    """graver_extract.  state: optional dict of float64 device tensors z, m, v
+    (N x d).  Returns (keys uint8-view int8 tensor count x n on the device,
+    stats dict)."""
+    import torch
+    n = prob.A.shape[1]
+    cap = params.pool_capacity if keys_cap is None else keys_cap
+    keys = torch.empty((max(cap, 1), n), dtype=torch.int8, device=prob.A.device)
+    cnt = C.c_int64(0)
+    stats = ExtractStats()
+    st = None
+    if state is not None:
+        st = State(_ptr(state.get("z")), _ptr(state.get("m")), _ptr(state.get("v")))
+    pc = prob.c()
+    _check(lib().graver_extract(ctx.h, C.byref(pc), C.byref(params), C.byref(st) if st else None,
+                                keys.data_ptr(), cap, C.byref(cnt), C.byref(stats)))
+    return keys[: cnt.value], stats.as_dict()
+
+
+def filter_minimal(ctx: Context, keys, keys_cap=None):
+    """graver_filter on an int8 device tensor (count x n)."""
+    import torch
+    count, n = keys.shape
+    keys = keys.contiguous()
+    cap = count if keys_cap is None else keys_cap
+    out = torch.empty((max(cap, 1), n), dtype=torch.int8, device=keys.device)
+    cnt = C.c_int64(0)
+    _check(lib().graver_filter(ctx.h, n, keys.data_ptr() if count else None, count, out.data_ptr(), cap,
+                               C.byref(cnt)))
+    return out[: cnt.value]
+
+
+def objective(kind: str, Q=None, c=None, coef=None, device="cuda"):
+    """Device tensors + ObjectiveC for graver_augment."""
+    import torch
+    t = lambda x: None if x is None else torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=device)
+    if kind == "quadratic":
+        Qt, ct = t(Q), t(c)
+        return (Qt, ct), ObjectiveC(GRAVER_F_QUADRATIC, 0, _ptr(Qt), _ptr(ct), None)
+    cf = t(coef)
+    return (cf,), ObjectiveC(GRAVER_F_SEPARABLE_POLY, int(coef.shape[1]) - 1, None, None, _ptr(cf))
+
+
+def augment(ctx: Context, prob: DeviceProblem, obj, dirs, x_starts, max_steps: int = 10 ** 6):
+    """graver_augment.  obj = the pair returned by objective().  Returns
+    (x_out, f_out, steps_out) device tensors and the best start index."""
+    import torch
+    _, oc = obj
+    S, n = x_starts.shape
+    x_starts = x_starts.contiguous()
+    dirs = dirs.contiguous()
+    x_out = torch.empty_like(x_starts)
+    f_out = torch.empty(S, dtype=torch.float64, device=x_starts.device)
+    steps = torch.empty(S, dtype=torch.int64, device=x_starts.device)
+    best = C.c_int32(-1)
+    pc = prob.c()
+    prm = AugmentParams(max_steps)
+    _check(lib().graver_augment(ctx.h, C.byref(pc), C.byref(oc), dirs.data_ptr() if dirs.shape[0] else None,
+                                dirs.shape[0], S, x_starts.data_ptr(), C.byref(prm), x_out.data_ptr(),
+                                f_out.data_ptr(), steps.data_ptr(), C.byref(best)))
+    return x_out, f_out, steps, best.value

@@ -1,0 +1,69 @@
+"""Host-side checks of the C-ABI library (no GPU compute): it loads,
+exports every declared entry point, and its host kernel basis matches the
+oracle bit for bit."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import lattice
+from paper_2412_13576_amd import graver as G
+from paper_2412_13576_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "graver.h")).read()
+    return sorted(set(re.findall(r"\b(graver_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = G.lib()
+    names = _declared()
+    assert set(G.EXPORTED) == set(names)
+    for name in names:
+        assert hasattr(L, name), name
+
+
+INSTANCES = [W.tiny_instance(s) for s in range(1000, 1005)] + [
+    W.random_instance(7, 3, 9), W.random_instance(8, 4, 12, density=0.5), W.qp_instance(2000)]
+
+
+@pytest.mark.parametrize("inst", INSTANCES, ids=[i.name for i in INSTANCES])
+@pytest.mark.parametrize("lll", [False, True])
+def test_host_kernel_basis_matches_oracle(inst, lll):
+    B, P = G.kernel_basis(inst.A, lll=lll)
+    Bo = lattice.kernel_basis(inst.A, lll=lll)
+    assert np.array_equal(B, Bo)
+    assert np.all(inst.A @ B == 0)
+    if lll and inst.n <= 12:
+        Po = lattice.coordinate_projector(Bo)
+        assert np.allclose(P, Po, rtol=1e-13, atol=1e-15)
+
+
+def test_host_kernel_basis_rank_deficient_and_errors():
+    A = np.array([[1, 2, 3, 4], [2, 4, 6, 8]])
+    B, P = G.kernel_basis(A)
+    assert B.shape == (4, 3) and np.array_equal(B, lattice.kernel_basis(A))
+    with pytest.raises(G.GraverError) as e:
+        G.lib()  # loaded
+        import ctypes as C
+        d = C.c_int32(0)
+        G._check(G.lib().graver_kernel_basis(0, 4, None, 1, None, C.byref(d), None))
+    assert e.value.status == -1
+
+
+def test_host_kernel_basis_overflow_is_reported():
+    # The exact K of this A has entries of 150+ bits, which int64 cannot hold.
+    A = np.array([[2 ** 40 + 1, 2 ** 40 + 3, 5], [7, 11, 2 ** 40 + 13]], dtype=np.int64)
+    h = lattice.hnf_kernel_basis(A)
+    assert max(abs(v) for row in h["K"] for v in row) >= 2 ** 63
+    with pytest.raises(G.GraverError) as e:
+        G.kernel_basis(A, lll=False)
+    assert e.value.status == -4
+    # large but representable entries still match the oracle exactly
+    A = np.array([[2 ** 50 + 1, 2 ** 50 + 3, 2 ** 49 + 5]], dtype=np.int64)
+    B, _ = G.kernel_basis(A, lll=False)
+    assert np.array_equal(B, np.array(lattice.hnf_kernel_basis(A)["B"], dtype=np.int64))
