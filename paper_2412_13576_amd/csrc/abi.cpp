@@ -300,7 +300,6 @@ graver_status graver_extract(graver_ctx* ctx, const graver_problem* prob,
   da.collect = prm->collect;
 
   {
-    EventTimer tm(s);
     if (prm->precision == GRAVER_FP64) {
       double* rp = (double*)ws_get(ctx, WS_RPREV, nd * sizeof(double), &st);
       if (!rp) return st;
@@ -309,7 +308,9 @@ graver_status graver_extract(graver_ctx* ctx, const graver_problem* prob,
       int8_t* ks = (int8_t*)ws_get(ctx, WS_KEYSCRATCH, (size_t)N * pool.stride, &st);
       if (!ks) return st;
       HIP_TRY(hipMemsetAsync(rp, 0xFF, nd * sizeof(double), s), "rprev = NaN");
+      EventTimer tm(s);
       if (T > 0) HIP_TRY(launch_descent_fp64(s, da, z, mm, vv, rp, sg, ks, pool, counters), "descent fp64");
+      stt.ms_descent = tm.stop_ms();
     } else {
       if (!descent_f32_supported(n, d))
         return set_error(GRAVER_E_INVALID, "FP32 descent supports n <= 128, d <= 128 in this build");
@@ -327,11 +328,12 @@ graver_status graver_extract(graver_ctx* ctx, const graver_problem* prob,
       HIP_TRY(hipStreamSynchronize(s), "sync");
       float zrange = (float)std::min(1073741824.0, std::floor(16777216.0 / std::max(hrow, 1)));
       HIP_TRY(launch_f32_state_io(s, n, d, N, fstate, z, mm, vv, 1), "state in");
+      EventTimer tm(s);
       if (T > 0)
         HIP_TRY(launch_descent_f32(s, da, Bp, BTp, fstate, pool, counters, zrange), "descent fp32");
+      stt.ms_descent = tm.stop_ms();
       HIP_TRY(launch_f32_state_io(s, n, d, N, fstate, z, mm, vv, 0), "state out");
     }
-    stt.ms_descent = tm.stop_ms();
   }
   HIP_TRY(hipGetLastError(), "descent launch");
 

@@ -1,22 +1,429 @@
-// Binary32 descent on MFMA (placeholder until the MFMA kernel lands).
+// Binary32 descent of eq. loss with Parallel Extraction (Algorithm 2) on
+// gfx950 matrix cores.
+//
+// One wave owns 16 starts for the whole call; their z, m, v stay in
+// registers.  Both contractions run on v_mfma_f32_16x16x4_f32 in transposed
+// form so that no data moves between them:
+//   forward   Y^T (n x 16) = B   (n x d) * Z^T (d x 16)
+//   backward  G^T (d x 16) = B^T (d x n) * sign(Y)^T (n x 16)
+// In a 16x16x4 MFMA, lane l supplies A[l%16][l/16] and B[l/16][l%16] and
+// receives D[4*(l/16)+r][l%16], r = 0..3.  With the K index of the r-th
+// MFMA of a 16-block mapped to rows 4k+r, the forward result held by lane l
+// (rows 4*(l/16)+r of start l%16) is exactly the backward B operand it
+// must supply, and the backward result has the layout of z.  The A
+// operands (entries of B) come from LDS, pre-packed so each lane reads one
+// float4 per 16x16 block.
+//
+// After the Adam step every coordinate is rounded (ties to even).  The
+// exact candidate g = B r of every start is tracked incrementally:
+// g += B (r - r_prev) runs on the same MFMA only for the 4-column groups in
+// which some start's rounded coordinate moved; every partial sum is an
+// integer below 2^24 as long as |z_j| < floor(2^24 / max_i sum_j |B_ij|),
+// so binary32 accumulation is exact.  A start whose iterate leaves that
+// range stops collecting (counted as out of range).  When a start's r
+// changed and g is nonzero and inside [l - u, u - l], its int8 key is
+// assembled in LDS and inserted into the device pool.
 #include <hip/hip_runtime.h>
 
 #include "graver_internal.h"
+#include "pool_device.h"
 
 namespace graver {
 
-bool descent_f32_supported(int, int) { return false; }
-size_t f32_pack_floats(int n, int d) { return (size_t)n * d; }
-size_t f32_state_floats(int n, int d, int64_t N) { return (size_t)N * d * 3; }
-hipError_t launch_f32_pack(hipStream_t, int, int, const int64_t*, float*, float*, int*) {
-  return hipErrorNotSupported;
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kWavesPerBlock = 4;
+constexpr int kMaxBlk = 8;  // n, d <= 128
+
+bool descent_f32_supported(int n, int d) { return n <= 16 * kMaxBlk && d <= 16 * kMaxBlk && d <= n; }
+
+static inline int blk(int x) { return (x + 15) / 16; }
+
+size_t f32_pack_floats(int n, int d) { return (size_t)blk(n) * blk(d) * 64 * 4; }
+
+static inline int64_t n_waves(int64_t N) {
+  int64_t w = (N + 15) / 16;
+  return (w + kWavesPerBlock - 1) / kWavesPerBlock * kWavesPerBlock;
 }
-hipError_t launch_f32_state_io(hipStream_t, int, int, int64_t, float*, double*, double*, double*, int) {
-  return hipErrorNotSupported;
+
+size_t f32_state_floats(int n, int d, int64_t N) {
+  (void)n;
+  return 3 * (size_t)n_waves(N) * 4 * blk(d) * 64;
 }
-hipError_t launch_descent_f32(hipStream_t, const DescentArgs&, const float*, const float*, float*, PoolDev,
-                              unsigned long long*, float) {
-  return hipErrorNotSupported;
+
+// FA[(ib*DB + jb)*64 + l] = (B[16ib + l%16][16jb + 4(l/16) + r], r = 0..3)
+// BA[(jb*NB + ib)*64 + l] = (B[16ib + 4(l/16) + r][16jb + l%16], r = 0..3)
+__global__ void k_pack(int n, int d, int NB, int DB, const int64_t* B, float* FA, float* BA) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  int total = NB * DB * 64;
+  if (t >= total) return;
+  int l = t % 64, blkid = t / 64;
+  {
+    int ib = blkid / DB, jb = blkid % DB;
+    int i = 16 * ib + l % 16;
+    for (int r = 0; r < 4; ++r) {
+      int j = 16 * jb + 4 * (l / 16) + r;
+      FA[(size_t)t * 4 + r] = (i < n && j < d) ? (float)B[(size_t)i * d + j] : 0.f;
+    }
+  }
+  {
+    int jb = blkid / NB, ib = blkid % NB;
+    int j = 16 * jb + l % 16;
+    for (int r = 0; r < 4; ++r) {
+      int i = 16 * ib + 4 * (l / 16) + r;
+      BA[(size_t)t * 4 + r] = (i < n && j < d) ? (float)B[(size_t)i * d + j] : 0.f;
+    }
+  }
+}
+
+__global__ void k_rowl1(int n, int d, const int64_t* B, int* out) {
+  __shared__ int sh[256];
+  int best = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    int64_t s = 0;
+    for (int j = 0; j < d; ++j) {
+      int64_t b = B[(size_t)i * d + j];
+      s += b < 0 ? -b : b;
+    }
+    best = max(best, (int)min<int64_t>(s, 1 << 30));
+  }
+  sh[threadIdx.x] = best;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] = max(sh[threadIdx.x], sh[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sh[0];
+}
+
+hipError_t launch_f32_pack(hipStream_t s, int n, int d, const int64_t* B, float* Bp, float* BTp, int* rowl1) {
+  int NB = blk(n), DB = blk(d);
+  int total = NB * DB * 64;
+  hipLaunchKernelGGL(k_pack, dim3((total + 255) / 256), dim3(256), 0, s, n, d, NB, DB, B, Bp, BTp);
+  hipLaunchKernelGGL(k_rowl1, dim3(1), dim3(256), 0, s, n, d, B, rowl1);
+  return hipGetLastError();
+}
+
+// Conversion between N x d binary64 arrays and the wave-native layout:
+// element (s, j) lives at ((w*4DB + 4*jb + r) * 64 + 16*q + s%16) with
+// w = s/16, jb = j/16, q = (j%16)/4, r = j%4.
+__global__ void k_state_io(int d, int DB, int64_t N, int64_t nw, float* state, double* z, double* m,
+                           double* v, int to_device) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t per = nw * 4 * DB * 64;
+  if (t >= per) return;
+  int l = (int)(t % 64);
+  int64_t rest = t / 64;
+  int rho = (int)(rest % (4 * DB));
+  int64_t w = rest / (4 * DB);
+  int jb = rho / 4, r = rho % 4;
+  int64_t s = w * 16 + (l % 16);
+  int j = 16 * jb + 4 * (l / 16) + r;
+  bool valid = s < N && j < d;
+  size_t e = (size_t)s * d + j;
+  if (to_device) {
+    state[t] = valid ? (float)z[e] : 0.f;
+    state[per + t] = valid && m ? (float)m[e] : 0.f;
+    state[2 * per + t] = valid && v ? (float)v[e] : 0.f;
+  } else if (valid) {
+    z[e] = (double)state[t];
+    if (m) m[e] = (double)state[per + t];
+    if (v) v[e] = (double)state[2 * per + t];
+  }
+}
+
+hipError_t launch_f32_state_io(hipStream_t s, int n, int d, int64_t N, float* state, double* z, double* m,
+                               double* v, int to_device) {
+  (void)n;
+  int DB = blk(d);
+  int64_t nw = n_waves(N);
+  int64_t per = nw * 4 * DB * 64;
+  hipLaunchKernelGGL(k_state_io, dim3((unsigned)((per + 255) / 256)), dim3(256), 0, s, d, DB, N, nw, state, z,
+                     m, v, to_device);
+  return hipGetLastError();
+}
+
+__device__ __forceinline__ float sgnf(float y) { return y > 0.f ? 1.f : (y < 0.f ? -1.f : 0.f); }
+
+__device__ __forceinline__ float xmax4(float x) {
+  x = fmaxf(x, __shfl_xor(x, 16, 64));
+  return fmaxf(x, __shfl_xor(x, 32, 64));
+}
+__device__ __forceinline__ float xsum4(float x) {
+  x += __shfl_xor(x, 16, 64);
+  return x + __shfl_xor(x, 32, 64);
+}
+__device__ __forceinline__ int xor4(int x) {
+  x |= __shfl_xor(x, 16, 64);
+  return x | __shfl_xor(x, 32, 64);
+}
+__device__ __forceinline__ int xand4(int x) {
+  x &= __shfl_xor(x, 16, 64);
+  return x & __shfl_xor(x, 32, 64);
+}
+
+template <int NB, int DB>
+__global__ __launch_bounds__(64 * kWavesPerBlock, 2) void k_descent_f32(DescentArgs a, const floatx4* __restrict__ FA,
+                                                                         const floatx4* __restrict__ BA,
+                                                                         float* __restrict__ state, PoolDev pool,
+                                                                         unsigned long long* counters,
+                                                                         float zrange, int64_t per) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  floatx4* sFA = reinterpret_cast<floatx4*>(smem);
+  floatx4* sBA = sFA + NB * DB * 64;
+  int* sLim = reinterpret_cast<int*>(sBA + NB * DB * 64);
+  int8_t* sKeys = reinterpret_cast<int8_t*>(sLim + 16 * NB);
+  const int stride = pool.stride;
+
+  for (int t = threadIdx.x; t < NB * DB * 64; t += blockDim.x) {
+    sFA[t] = FA[t];
+    sBA[t] = BA[t];
+  }
+  for (int i = threadIdx.x; i < 16 * NB; i += blockDim.x)
+    sLim[i] = i < a.n ? (int)(a.u[i] - a.l[i]) : 0;
+  for (int t = threadIdx.x; t < kWavesPerBlock * 16 * stride; t += blockDim.x) sKeys[t] = 0;
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int q = lane >> 4, sl = lane & 15;
+  const int64_t w = (int64_t)blockIdx.x * kWavesPerBlock + wid;
+  const int64_t sidx = w * 16 + sl;
+  const bool svalid = sidx < a.N;
+  int8_t* myKeys = sKeys + wid * 16 * stride;
+
+  float z[DB][4], m[DB][4], v[DB][4], rp[DB][4];
+  int gi[NB][4];
+  const size_t base = (size_t)w * 4 * DB * 64 + lane;
+#pragma unroll
+  for (int jb = 0; jb < DB; ++jb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      size_t e = base + (size_t)(4 * jb + r) * 64;
+      z[jb][r] = state[e];
+      m[jb][r] = state[per + e];
+      v[jb][r] = state[2 * per + e];
+      rp[jb][r] = 0.f;
+    }
+#pragma unroll
+  for (int ib = 0; ib < NB; ++ib)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) gi[ib][r] = 0;
+
+  bool alive = svalid;
+  unsigned long long n_emit = 0, n_inbox = 0, n_range = 0;
+  const float lam1 = (float)a.lambda1, lam2 = (float)a.lambda2;
+  const float b1 = (float)a.beta1, b2 = (float)a.beta2, omb1 = (float)a.one_minus_b1, omb2 = (float)a.one_minus_b2;
+  const float eps = (float)a.eps;
+
+  for (int k = 0; k < a.T; ++k) {
+    // ---- forward Y^T = B Z^T, then signs (kept in the accumulators) ----
+    floatx4 acc[NB];
+#pragma unroll
+    for (int ib = 0; ib < NB; ++ib) acc[ib] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int jb = 0; jb < DB; ++jb) {
+      floatx4 A[NB];
+#pragma unroll
+      for (int ib = 0; ib < NB; ++ib) A[ib] = sFA[(ib * DB + jb) * 64 + lane];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int ib = 0; ib < NB; ++ib)
+          acc[ib] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[ib][r], z[jb][r], acc[ib], 0, 0, 0);
+    }
+#pragma unroll
+    for (int ib = 0; ib < NB; ++ib)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[ib][r] = sgnf(acc[ib][r]);
+    // ---- backward G^T = B^T sign(Y)^T ----
+    floatx4 gacc[DB];
+#pragma unroll
+    for (int jb = 0; jb < DB; ++jb) gacc[jb] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ib = 0; ib < NB; ++ib) {
+      floatx4 A[DB];
+#pragma unroll
+      for (int jb = 0; jb < DB; ++jb) A[jb] = sBA[(jb * NB + ib) * 64 + lane];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int jb = 0; jb < DB; ++jb)
+          gacc[jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[jb][r], acc[ib][r], gacc[jb], 0, 0, 0);
+    }
+    // ---- barrier term: ||z||_inf and ties, per start (4 lanes) ----
+    float mu = 0.f;
+#pragma unroll
+    for (int jb = 0; jb < DB; ++jb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) mu = fmaxf(mu, fabsf(z[jb][r]));
+    mu = xmax4(mu);
+    float cnt = 0.f;
+#pragma unroll
+    for (int jb = 0; jb < DB; ++jb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) cnt += fabsf(z[jb][r]) == mu ? 1.f : 0.f;
+    cnt = xsum4(cnt);
+    const bool bar = mu > 0.f && mu < 1.f;
+    const float wbar = bar ? lam2 / ((mu * mu) * cnt) : 0.f;
+    const double bc1 = a.bc[2 * k], bc2 = a.bc[2 * k + 1];
+    const float step = (float)(a.lr / bc1), ib2 = (float)(1.0 / bc2);
+    // ---- gradient, Adam, rounding ----
+    int changed = 0, inrange = 1;
+    floatx4 dr[DB];
+#pragma unroll
+    for (int jb = 0; jb < DB; ++jb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float zj = z[jb][r];
+        float g = gacc[jb][r] + lam1 * ((ceilf(zj) + floorf(zj)) - 2.f * zj);
+        if (bar && fabsf(zj) == mu) g -= zj > 0.f ? wbar : -wbar;
+        const float mj = b1 * m[jb][r] + omb1 * g;
+        const float vj = b2 * v[jb][r] + omb2 * (g * g);
+        m[jb][r] = mj;
+        v[jb][r] = vj;
+        const float zn = zj - __fdividef(step * mj, __fsqrt_rn(vj * ib2) + eps);
+        z[jb][r] = zn;
+        const float rn = rintf(zn);
+        changed |= (rn != rp[jb][r]) | (k == 0);
+        inrange &= fabsf(zn) < zrange;
+        dr[jb][r] = rn - rp[jb][r];
+        rp[jb][r] = rn;
+      }
+    if (!a.collect) continue;
+    // ---- per-start flags (the 4 lanes of a start agree afterwards) ----
+    inrange = xand4(inrange);
+    changed = xor4(changed);
+    if (alive && !inrange) alive = false;
+    if (!alive) {
+      n_range += (q == 0 && svalid) ? 1 : 0;
+#pragma unroll
+      for (int jb = 0; jb < DB; ++jb) dr[jb] = floatx4{0.f, 0.f, 0.f, 0.f};
+    }
+    const bool emit = alive && changed;
+    // ---- exact candidate update g += B (r - r_prev) on changed groups ----
+    floatx4 dg[NB];
+    bool any = false;
+#pragma unroll
+    for (int ib = 0; ib < NB; ++ib) dg[ib] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int jb = 0; jb < DB; ++jb) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (__ballot(dr[jb][r] != 0.f) == 0) continue;
+        any = true;
+#pragma unroll
+        for (int ib = 0; ib < NB; ++ib)
+          dg[ib] = __builtin_amdgcn_mfma_f32_16x16x4f32(sFA[(ib * DB + jb) * 64 + lane][r], dr[jb][r], dg[ib], 0,
+                                                         0, 0);
+      }
+    }
+    if (any) {
+#pragma unroll
+      for (int ib = 0; ib < NB; ++ib)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) gi[ib][r] += (int)dg[ib][r];
+    }
+    if (__ballot(emit) == 0) continue;
+    // ---- box test (condition C4) and nonzero test ----
+    int inbox = 1, nonzero = 0;
+#pragma unroll
+    for (int ib = 0; ib < NB; ++ib)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * ib + 4 * q + r;
+        const int g = gi[ib][r];
+        const int lim = sLim[i];
+        inbox &= (g <= lim) & (g >= -lim);
+        nonzero |= g != 0;
+      }
+    inbox = xand4(inbox);
+    nonzero = xor4(nonzero);
+    const bool put = emit && inbox && nonzero;
+    n_emit += (q == 0 && emit) ? 1 : 0;
+    n_inbox += (q == 0 && put) ? 1 : 0;
+    if (__ballot(put) == 0) continue;
+    if (put) {
+#pragma unroll
+      for (int ib = 0; ib < NB; ++ib)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = 16 * ib + 4 * q + r;
+          if (i < a.n) myKeys[sl * stride + i] = (int8_t)gi[ib][r];
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (q == 0 && put) {
+      const uint64_t* key = reinterpret_cast<const uint64_t*>(myKeys + sl * stride);
+      uint64_t h = hash_key_words(key, stride / 8);
+      pool_insert(pool, key, h);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+#pragma unroll
+  for (int jb = 0; jb < DB; ++jb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      size_t e = base + (size_t)(4 * jb + r) * 64;
+      state[e] = z[jb][r];
+      state[per + e] = m[jb][r];
+      state[2 * per + e] = v[jb][r];
+    }
+  // wave-reduce the counters, one atomic per wave
+  for (int o = 32; o > 0; o >>= 1) {
+    n_emit += __shfl_xor(n_emit, o, 64);
+    n_inbox += __shfl_xor(n_inbox, o, 64);
+    n_range += __shfl_xor(n_range, o, 64);
+  }
+  if (lane == 0) {
+    if (n_emit) atomicAdd(&counters[C_EMIT], n_emit);
+    if (n_inbox) atomicAdd(&counters[C_INBOX], n_inbox);
+    if (n_range) atomicAdd(&counters[C_RANGE], n_range);
+  }
+}
+
+template <int NB, int DB>
+static hipError_t launch_nd(hipStream_t s, const DescentArgs& a, const float* FA, const float* BA, float* state,
+                            PoolDev pool, unsigned long long* counters, float zrange) {
+  const int64_t nw = n_waves(a.N);
+  const int64_t per = nw * 4 * DB * 64;
+  const size_t shmem = (size_t)2 * NB * DB * 64 * sizeof(floatx4) + 16 * NB * sizeof(int) +
+                       (size_t)kWavesPerBlock * 16 * pool.stride;
+  auto kern = k_descent_f32<NB, DB>;
+  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3((unsigned)(nw / kWavesPerBlock)), dim3(64 * kWavesPerBlock), shmem, s, a,
+                     reinterpret_cast<const floatx4*>(FA), reinterpret_cast<const floatx4*>(BA), state, pool,
+                     counters, zrange, per);
+  return hipGetLastError();
+}
+
+template <int NB, int DB>
+static hipError_t dispatch_d(int db, hipStream_t s, const DescentArgs& a, const float* FA, const float* BA,
+                             float* st, PoolDev p, unsigned long long* c, float zr) {
+  if constexpr (DB > NB) {
+    return hipErrorInvalidValue;
+  } else {
+    if (db == DB) return launch_nd<NB, DB>(s, a, FA, BA, st, p, c, zr);
+    if constexpr (DB > 1) return dispatch_d<NB, DB - 1>(db, s, a, FA, BA, st, p, c, zr);
+    return hipErrorInvalidValue;
+  }
+}
+
+template <int NB>
+static hipError_t dispatch_n(int nb, int db, hipStream_t s, const DescentArgs& a, const float* FA, const float* BA,
+                             float* st, PoolDev p, unsigned long long* c, float zr) {
+  if (nb == NB) return dispatch_d<NB, NB>(db, s, a, FA, BA, st, p, c, zr);
+  if constexpr (NB > 1) return dispatch_n<NB - 1>(nb, db, s, a, FA, BA, st, p, c, zr);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_descent_f32(hipStream_t s, const DescentArgs& a, const float* FA, const float* BA, float* state,
+                              PoolDev pool, unsigned long long* counters, float zrange) {
+  return dispatch_n<kMaxBlk>(blk(a.n), blk(a.d), s, a, FA, BA, state, pool, counters, zrange);
 }
 
 }  // namespace graver
