@@ -78,7 +78,7 @@ def main():
     obj = G.objective("quadratic", Q=inst.Q, c=inst.c)
     starts_h = W.feasible_walk_starts(inst.x0, B.T.copy(), inst.l, inst.u, S0, seed=7, walk_len=32)
     starts = torch.tensor(starts_h, device="cuda")
-    pool_cap = 4 * N * 8
+    pool_cap = 1 << 23
     keys_buf_cap = pool_cap
 
     def step(seed):
