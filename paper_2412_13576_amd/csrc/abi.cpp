@@ -201,9 +201,11 @@ graver_status graver_extract(graver_ctx* ctx, const graver_problem* prob,
     return set_error(GRAVER_E_INVALID, "bad output buffer");
 
   // B must be a kernel basis: A B = 0 exactly.
+  int a_small = 1;
   {
     std::vector<int64_t> hA, hB;
     if ((st = copy_to_host(ctx, hA, prob->A, (size_t)m * n)) != GRAVER_OK) return st;
+    for (int64_t av : hA) a_small &= (av > -(1 << 23) && av < (1 << 23)) ? 1 : 0;
     if ((st = copy_to_host(ctx, hB, prob->B, (size_t)n * d)) != GRAVER_OK) return st;
     for (int i = 0; i < m; ++i)
       for (int c = 0; c < d; ++c) {
@@ -369,7 +371,7 @@ graver_status graver_extract(graver_ctx* ctx, const graver_problem* prob,
     EventTimer tm(s);
     unsigned int* bad = (unsigned int*)ws_get(ctx, WS_FLAGS, 64, &st);
     if (!bad) return st;
-    HIP_TRY(launch_verify(s, pool, count, m, prob->A, bad), "verify");
+    HIP_TRY(launch_verify(s, pool, count, m, prob->A, bad, a_small), "verify");
     unsigned int hbad = 0;
     HIP_TRY(hipMemcpyAsync(&hbad, bad, sizeof(hbad), hipMemcpyDeviceToHost, s), "verify flag");
     stt.ms_verify = tm.stop_ms();

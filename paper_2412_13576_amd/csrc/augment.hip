@@ -59,24 +59,6 @@ __global__ void k_zero_i64(int64_t* a, size_t n) {
   if (i < n) a[i] = 0;
 }
 
-// q_g = sum_{i in supp} g_i * (sum_{j in supp} Q_ij g_j), ascending.
-__global__ void k_qg(int n, int K, const int8_t* __restrict__ F, const double* __restrict__ Q, double* qg) {
-  int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= K) return;
-  const int8_t* g = F + (size_t)k * n;
-  double q = 0.0;
-  for (int i = 0; i < n; ++i) {
-    if (g[i] == 0) continue;
-    double t = 0.0;
-    for (int j = 0; j < n; ++j) {
-      if (g[j] == 0) continue;
-      t = t + Q[(size_t)i * n + j] * (double)g[j];
-    }
-    q = q + (double)g[i] * t;
-  }
-  qg[k] = q;
-}
-
 // tab[i * w + (v - l_i)] = p_i(v) by Horner from the top coefficient.
 __global__ void k_poly_table(int n, int deg, int w, const double* coef, const int64_t* l, const int64_t* u,
                              double* tab) {
@@ -110,78 +92,130 @@ __global__ void k_prepare(AugArgs a, const int64_t* X, const uint32_t* done, con
 }
 
 constexpr int kEvalThreads = 256;
+constexpr int kStartGroup = 8;
 
-__global__ void k_eval(AugArgs a, const int64_t* X, const uint32_t* done, const double* R, const double* qg,
-                       const double* tab, int w, Move* partial) {
-  const int s = blockIdx.y;
-  if (done[s]) return;
+// q_g of one direction (ascending sums over its support), computed the
+// first time some start can move along g and cached for the call.
+__device__ double qg_of(const int8_t* g, int n, const double* Q) {
+  double q = 0.0;
+  for (int i = 0; i < n; ++i) {
+    if (g[i] == 0) continue;
+    double t = 0.0;
+    for (int j = 0; j < n; ++j) {
+      if (g[j] == 0) continue;
+      t = t + Q[(size_t)i * n + j] * (double)g[j];
+    }
+    q = q + (double)g[i] * t;
+  }
+  return q;
+}
+
+__device__ __forceinline__ void wave_best(Move& b) {
+  for (int o = 32; o > 0; o >>= 1) {
+    Move o2;
+    o2.delta = __shfl_xor(b.delta, o, 64);
+    o2.pos = __shfl_xor(b.pos, o, 64);
+    o2.lam = __shfl_xor(b.lam, o, 64);
+    if (better(o2, b)) b = o2;
+  }
+}
+
+// Thread = one direction g, looping over a group of starts.  A move along
+// +g or -g exists only if lambda = 1 is feasible (the box is convex and x
+// is inside it), which is tested first with an early exit; lambda_max,
+// a_g and q_g are computed only for feasible directions.
+__global__ void k_eval(AugArgs a, const int64_t* X, const uint32_t* done, const double* R, double* qg,
+                       uint32_t* qflag, const double* tab, int w, Move* partial) {
   const int n = a.n;
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t* x = X + (size_t)s * n;
-  const double* r = R + (size_t)s * n;
-  Move best{INFINITY, 0xFFFFFFFFu, 0};
-  if (k < a.K) {
-    const int8_t* g = a.dirs + (size_t)k * n;
-    // lambda_max for +g and -g
-    int64_t lp = INT64_MAX, ln = INT64_MAX;
-    bool any = false;
-    for (int i = 0; i < n; ++i) {
-      int gi = g[i];
-      if (gi == 0) continue;
-      any = true;
-      int64_t up = a.u[i] - x[i], dn = x[i] - a.l[i];
-      if (gi > 0) {
-        lp = min(lp, up / gi);
-        ln = min(ln, dn / gi);
-      } else {
-        lp = min(lp, dn / (-gi));
-        ln = min(ln, up / (-gi));
+  const int s0 = blockIdx.y * kStartGroup;
+  const int8_t* g = a.dirs + (size_t)(k < a.K ? k : 0) * n;
+  __shared__ Move sh[kStartGroup][kEvalThreads / 64];
+  for (int si = 0; si < kStartGroup; ++si) {
+    const int s = s0 + si;
+    Move best{INFINITY, 0xFFFFFFFFu, 0};
+    if (s < a.S && !done[s] && k < a.K) {
+      const int64_t* x = X + (size_t)s * n;
+      bool fp = true, fn = true, any = false;
+      for (int i = 0; i < n; ++i) {
+        const int gi = g[i];
+        if (gi == 0) continue;
+        any = true;
+        const int64_t xi = x[i], li = a.l[i], ui = a.u[i];
+        fp = fp && xi + gi >= li && xi + gi <= ui;
+        fn = fn && xi - gi >= li && xi - gi <= ui;
+        if (!fp && !fn) break;
       }
-    }
-    if (any) {
-      if (a.kind == GRAVER_F_QUADRATIC) {
-        double ag = 0.0;
+      if (any && (fp || fn)) {
+        int64_t lp = INT64_MAX, ln = INT64_MAX;
         for (int i = 0; i < n; ++i) {
-          int gi = g[i];
-          if (gi != 0) ag = ag + (double)gi * r[i];
-        }
-        const double q = qg[k];
-        for (int sg = 0; sg < 2; ++sg) {
-          const int64_t lm = sg ? ln : lp;
-          const double av = sg ? -ag : ag;
-          for (int64_t lam = 1; lam <= lm; ++lam) {
-            double lf = (double)lam;
-            Move mv{(lf * av) + ((lf * lf) * q), (uint32_t)(2 * k + sg), (int32_t)lam};
-            if (better(mv, best)) best = mv;
+          const int gi = g[i];
+          if (gi == 0) continue;
+          const int64_t up = a.u[i] - x[i], dn = x[i] - a.l[i];
+          if (gi > 0) {
+            lp = min(lp, up / gi);
+            ln = min(ln, dn / gi);
+          } else {
+            lp = min(lp, dn / (-gi));
+            ln = min(ln, up / (-gi));
           }
         }
-      } else {
-        for (int sg = 0; sg < 2; ++sg) {
-          const int64_t lm = sg ? ln : lp;
-          const int sgn = sg ? -1 : 1;
-          for (int64_t lam = 1; lam <= lm; ++lam) {
-            double acc = 0.0;
-            for (int i = 0; i < n; ++i) {
-              int gi = g[i];
-              if (gi == 0) continue;
-              int64_t v = x[i] + lam * sgn * gi;
-              acc = acc + (tab[(size_t)i * w + (v - a.l[i])] - r[i]);
+        const double* r = R + (size_t)s * n;
+        if (a.kind == GRAVER_F_QUADRATIC) {
+          double ag = 0.0;
+          for (int i = 0; i < n; ++i) {
+            const int gi = g[i];
+            if (gi != 0) ag = ag + (double)gi * r[i];
+          }
+          double q;
+          if (__hip_atomic_load(&qflag[k], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) {
+            q = __hip_atomic_load(&qg[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          } else {
+            q = qg_of(g, n, a.Q);
+            __hip_atomic_store(&qg[k], q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&qflag[k], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+          }
+          for (int sg = 0; sg < 2; ++sg) {
+            const int64_t lm = sg ? ln : lp;
+            const double av = sg ? -ag : ag;
+            for (int64_t lam = 1; lam <= lm; ++lam) {
+              double lf = (double)lam;
+              Move mv{(lf * av) + ((lf * lf) * q), (uint32_t)(2 * k + sg), (int32_t)lam};
+              if (better(mv, best)) best = mv;
             }
-            Move mv{acc, (uint32_t)(2 * k + sg), (int32_t)lam};
-            if (better(mv, best)) best = mv;
+          }
+        } else {
+          for (int sg = 0; sg < 2; ++sg) {
+            const int64_t lm = sg ? ln : lp;
+            const int sgn = sg ? -1 : 1;
+            for (int64_t lam = 1; lam <= lm; ++lam) {
+              double acc = 0.0;
+              for (int i = 0; i < n; ++i) {
+                const int gi = g[i];
+                if (gi == 0) continue;
+                const int64_t v = x[i] + lam * sgn * gi;
+                acc = acc + (tab[(size_t)i * w + (v - a.l[i])] - r[i]);
+              }
+              Move mv{acc, (uint32_t)(2 * k + sg), (int32_t)lam};
+              if (better(mv, best)) best = mv;
+            }
           }
         }
       }
     }
+    wave_best(best);
+    if ((threadIdx.x & 63) == 0) sh[si][threadIdx.x >> 6] = best;
   }
-  __shared__ Move sh[kEvalThreads];
-  sh[threadIdx.x] = best;
   __syncthreads();
-  for (int o = kEvalThreads / 2; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o && better(sh[threadIdx.x + o], sh[threadIdx.x])) sh[threadIdx.x] = sh[threadIdx.x + o];
-    __syncthreads();
+  if (threadIdx.x < kStartGroup) {
+    const int s = s0 + threadIdx.x;
+    if (s < a.S) {
+      Move best = sh[threadIdx.x][0];
+      for (int wv = 1; wv < kEvalThreads / 64; ++wv)
+        if (better(sh[threadIdx.x][wv], best)) best = sh[threadIdx.x][wv];
+      partial[(size_t)s * gridDim.x + blockIdx.x] = best;
+    }
   }
-  if (threadIdx.x == 0) partial[(size_t)s * gridDim.x + blockIdx.x] = sh[0];
 }
 
 __global__ void k_pick(AugArgs a, int nblk, const Move* partial, int64_t* X, uint32_t* done, int64_t* steps,
@@ -298,16 +332,17 @@ graver_status run_augment(graver_ctx* ctx, const AugArgs& a, const int64_t* x_st
   hipLaunchKernelGGL(k_copy_i64, dim3((unsigned)((sn + 255) / 256)), dim3(256), 0, s, x_starts, x_out, sn);
   hipLaunchKernelGGL(k_zero_u32, dim3((S + 255) / 256), dim3(256), 0, s, done, (size_t)S);
   hipLaunchKernelGGL(k_zero_i64, dim3((S + 255) / 256), dim3(256), 0, s, steps_out, (size_t)S);
-  if (K > 0 && a.kind == GRAVER_F_QUADRATIC)
-    hipLaunchKernelGGL(k_qg, dim3((K + 255) / 256), dim3(256), 0, s, n, K, a.dirs, a.Q, qg);
+  uint32_t* qflag = (uint32_t*)ws_get(ctx, WS_A_QFLAG, (size_t)(K > 0 ? K : 1) * 4 + 64, &st);
+  if (!qflag) return st;
+  if (K > 0) hipLaunchKernelGGL(k_zero_u32, dim3((K + 255) / 256), dim3(256), 0, s, qflag, (size_t)K);
 
   uint32_t* active = bad + 4;
   if (K > 0) {
     for (int64_t step = 0;; ++step) {
       hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, active, (size_t)1);
       hipLaunchKernelGGL(k_prepare, dim3((n + 127) / 128, S), dim3(128), 0, s, a, x_out, done, tab, w, R);
-      hipLaunchKernelGGL(k_eval, dim3(nblk, S), dim3(kEvalThreads), 0, s, a, x_out, done, R, qg, tab, w,
-                         partial);
+      hipLaunchKernelGGL(k_eval, dim3(nblk, (S + kStartGroup - 1) / kStartGroup), dim3(kEvalThreads), 0, s, a,
+                         x_out, done, R, qg, qflag, tab, w, partial);
       hipLaunchKernelGGL(k_pick, dim3(S), dim3(256), 0, s, a, nblk, partial, x_out, done, steps_out, active);
       uint32_t hact = 0;
       hipMemcpyAsync(&hact, active, 4, hipMemcpyDeviceToHost, s);

@@ -12,10 +12,18 @@
 //   output  : survivors, sorted lexicographically
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <vector>
+
 #include "graver_internal.h"
 #include "pool_device.h"
 
 namespace graver {
+
+__global__ void k_zero32(uint32_t* a, uint32_t n) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = 0;
+}
 
 __global__ void k_canon(const int8_t* in, int64_t count, int n, int stride, int8_t* out) {
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -157,7 +165,21 @@ __global__ void k_level_start(const int32_t* l1, uint32_t count, uint32_t* lo) {
   lo[p] = a;
 }
 
-constexpr int kTile = 64;
+// ---- witness search through a sign-pattern index -------------------------
+// A witness h of g (h conformally below g, or -h below g) must agree with
+// g's sign pattern wherever it is nonzero.  On a chosen set C of k
+// coordinates, every key gets the base-3 code of its signs (0 zero, 1
+// positive, 2 negative).  The witnesses of g for the relation "h below g"
+// can only have codes whose digits are 0 or g's digit, and for "-h below
+// g" digits that are 0 or the swapped digit; g enumerates these 2^z codes
+// (z = nonzeros of g on C) and tests only the keys of those buckets.  The
+// result is the same predicate as testing every pair.
+constexpr int kMaxC = 10;
+struct Coords {
+  int k;
+  int c[kMaxC];
+  int pow3[kMaxC];
+};
 
 __device__ __forceinline__ bool magnitude_below(const int8_t* h, const int8_t* g, int n) {
   for (int i = 0; i < n; ++i) {
@@ -167,51 +189,91 @@ __device__ __forceinline__ bool magnitude_below(const int8_t* h, const int8_t* g
   return true;
 }
 
-__global__ void k_pairs(const int8_t* keys, int stride, int n, uint32_t count, int W,
-                        const uint64_t* __restrict__ mask, const uint32_t* __restrict__ lo,
-                        uint32_t* alive) {
-  extern __shared__ uint64_t tile[];  // kTile x 2W
-  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool valid = p < count;
-  uint32_t my_lo = valid ? lo[p] : 0;
-  uint32_t last = min(count, (blockIdx.x + 1) * blockDim.x) - 1;
-  uint32_t block_hi = lo[last];
-  bool dead = false;
-  uint64_t gp[8], gn[8];
-  const int Wr = W < 8 ? W : 8;
-  if (valid) {
-    for (int w = 0; w < Wr; ++w) {
-      gp[w] = mask[(size_t)p * 2 * W + w];
-      gn[w] = mask[(size_t)p * 2 * W + W + w];
-    }
+// nonzero count of every coordinate; block = 1024 rows, thread = column
+__global__ void k_col_nnz(const int8_t* keys, int stride, int n, uint32_t count, uint32_t* cnt) {
+  uint32_t r0 = blockIdx.x * 1024u;
+  uint32_t r1 = min(count, r0 + 1024u);
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    uint32_t local = 0;
+    for (uint32_t r = r0; r < r1; ++r) local += keys[(size_t)r * stride + c] != 0;
+    if (local) atomicAdd(&cnt[c], local);
   }
+}
+
+__global__ void k_codes(const int8_t* keys, int stride, uint32_t count, Coords C, uint32_t* code,
+                        uint32_t* hist) {
+  uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= count) return;
   const int8_t* g = keys + (size_t)p * stride;
-  for (uint32_t base = 0; base < block_hi; base += kTile) {
-    __syncthreads();
-    for (int t = threadIdx.x; t < kTile * 2 * W; t += blockDim.x) {
-      uint32_t h = base + t / (2 * W);
-      tile[t] = h < count ? mask[(size_t)base * 2 * W + t] : 0ull;
-    }
-    __syncthreads();
-    if (!valid || dead || base >= my_lo) continue;
-    uint32_t hend = min((uint32_t)kTile, my_lo - base);
-    for (uint32_t q = 0; q < hend && !dead; ++q) {
-      const uint64_t* hm = tile + (size_t)q * 2 * W;
-      bool plus = true, minus = true;
-      for (int w = 0; w < W && (plus || minus); ++w) {
-        uint64_t hp = hm[w], hn = hm[W + w];
-        uint64_t mp = w < 8 ? gp[w] : mask[(size_t)p * 2 * W + w];
-        uint64_t mn = w < 8 ? gn[w] : mask[(size_t)p * 2 * W + W + w];
-        plus = plus && ((hp & ~mp) | (hn & ~mn)) == 0;
-        minus = minus && ((hp & ~mn) | (hn & ~mp)) == 0;
+  uint32_t cd = 0;
+  for (int i = 0; i < C.k; ++i) {
+    int v = g[C.c[i]];
+    cd += (v > 0 ? 1u : (v < 0 ? 2u : 0u)) * (uint32_t)C.pow3[i];
+  }
+  code[p] = cd;
+  atomicAdd(&hist[cd], 1u);
+}
+
+__global__ void k_bucket_scatter(const uint32_t* code, uint32_t count, const uint32_t* off, uint32_t* cur,
+                                 uint32_t* bl) {
+  uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= count) return;
+  uint32_t cd = code[p];
+  bl[off[cd] + atomicAdd(&cur[cd], 1u)] = p;
+}
+
+__global__ void k_pairs_bucket(const int8_t* keys, int stride, int n, uint32_t count, int W,
+                               const uint64_t* __restrict__ mask, const uint32_t* __restrict__ lo,
+                               const uint32_t* __restrict__ off, const uint32_t* __restrict__ bl, Coords C,
+                               uint32_t* alive) {
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= count) return;
+  const int8_t* g = keys + (size_t)p * stride;
+  const uint32_t my_lo = lo[p];
+  const uint64_t* gm = mask + (size_t)p * 2 * W;
+  bool dead = false;
+  if (my_lo > 0) {
+    int cp[kMaxC], cn[kMaxC];
+    int z = 0;
+    for (int i = 0; i < C.k; ++i) {
+      int v = g[C.c[i]];
+      if (v != 0) {
+        int dgt = v > 0 ? 1 : 2;
+        cp[z] = dgt * C.pow3[i];
+        cn[z] = (3 - dgt) * C.pow3[i];
+        ++z;
       }
-      if (plus || minus) {
-        const int8_t* h = keys + (size_t)(base + q) * stride;
-        if (magnitude_below(h, g, n)) dead = true;
+    }
+    const uint32_t nsub = 1u << z;
+    for (int pol = 0; pol < 2 && !dead; ++pol) {
+      int code = 0;
+      for (uint32_t sidx = 0; sidx < nsub && !dead; ++sidx) {
+        if (sidx) {
+          int t = __builtin_ctz(sidx);
+          uint32_t gray = sidx ^ (sidx >> 1);
+          int cv = pol ? cn[t] : cp[t];
+          code += ((gray >> t) & 1u) ? cv : -cv;
+        }
+        const uint32_t e1 = off[code + 1];
+        for (uint32_t e = off[code]; e < e1; ++e) {
+          const uint32_t h = bl[e];
+          if (h >= my_lo) continue;
+          const uint64_t* hm = mask + (size_t)h * 2 * W;
+          bool ok = true;
+          for (int w = 0; w < W && ok; ++w) {
+            uint64_t hp = hm[w], hn = hm[W + w];
+            uint64_t gp = gm[w], gn = gm[W + w];
+            ok = pol ? ((hp & ~gn) | (hn & ~gp)) == 0 : ((hp & ~gp) | (hn & ~gn)) == 0;
+          }
+          if (ok && magnitude_below(keys + (size_t)h * stride, g, n)) {
+            dead = true;
+            break;
+          }
+        }
       }
     }
   }
-  if (valid) alive[p] = dead ? 0u : 1u;
+  alive[p] = dead ? 0u : 1u;
 }
 
 hipError_t launch_filter(hipStream_t s, graver_ctx* ctx, int n, const int8_t* in, int64_t count_in,
@@ -257,8 +319,55 @@ hipError_t launch_filter(hipStream_t s, graver_ctx* ctx, int n, const int8_t* in
   hipLaunchKernelGGL(k_gather_rows, dim3(u256), dim3(256), 0, s, uniq, stride, idx, U, canon, l1, l1b,
                      msk, mskb, W);
   hipLaunchKernelGGL(k_level_start, dim3(u256), dim3(256), 0, s, l1b, U, lo);
-  size_t shmem = (size_t)kTile * 2 * W * sizeof(uint64_t);
-  hipLaunchKernelGGL(k_pairs, dim3(u256), dim3(256), shmem, s, canon, stride, n, U, W, mskb, lo, alive);
+  // sign-pattern index on the k most frequently nonzero coordinates
+  Coords C{};
+  {
+    int k = 0;
+    if (U >= 64) {
+      int lg = 0;
+      while ((1u << (lg + 1)) <= U) ++lg;
+      k = (lg + 1) / 2;
+    }
+    k = k < kMaxC ? k : kMaxC;
+    k = k < n ? k : n;
+    std::vector<uint32_t> hc(n, 0);
+    if (k > 0) {
+      uint32_t* cnt = (uint32_t*)ws_get(ctx, WS_F_CODE, ((size_t)U + n + 64) * 4, st);
+      if (!cnt) return hipSuccess;
+      hipLaunchKernelGGL(k_zero32, dim3((n + 255) / 256), dim3(256), 0, s, cnt, (uint32_t)n);
+      hipLaunchKernelGGL(k_col_nnz, dim3((U + 1023) / 1024), dim3(256), 0, s, canon, stride, n, U, cnt);
+      hipMemcpyAsync(hc.data(), cnt, (size_t)n * 4, hipMemcpyDeviceToHost, s);
+      e = hipStreamSynchronize(s);
+      if (e != hipSuccess) return e;
+    }
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return hc[a] > hc[b]; });
+    C.k = k;
+    int pw = 1;
+    for (int i = 0; i < k; ++i) {
+      C.c[i] = order[i];
+      C.pow3[i] = pw;
+      pw *= 3;
+    }
+  }
+  uint32_t ncode = 1;
+  for (int i = 0; i < C.k; ++i) ncode *= 3;
+  uint32_t* code = (uint32_t*)ws_get(ctx, WS_F_CODE, ((size_t)U + n + 64) * 4, st);
+  uint32_t* hist = (uint32_t*)ws_get(ctx, WS_F_HIST, ((size_t)ncode + 64) * 4, st);
+  uint32_t* boff = (uint32_t*)ws_get(ctx, WS_F_OFF, ((size_t)ncode + 64) * 4, st);
+  uint32_t* cur = (uint32_t*)ws_get(ctx, WS_F_CUR, ((size_t)ncode + 64) * 4, st);
+  uint32_t* bl = (uint32_t*)ws_get(ctx, WS_F_BL, (size_t)U * 4 + 64, st);
+  uint32_t* scr2 = (uint32_t*)ws_get(ctx, WS_SCAN2, (((size_t)cnt > ncode ? cnt : ncode) / 512 + 256) * 4, st);
+  if (!code || !hist || !boff || !cur || !bl || !scr2) return hipSuccess;
+  const unsigned c256 = (ncode + 1 + 255) / 256;
+  hipLaunchKernelGGL(k_zero32, dim3(c256), dim3(256), 0, s, hist, ncode + 1);
+  hipLaunchKernelGGL(k_zero32, dim3(c256), dim3(256), 0, s, cur, ncode + 1);
+  hipLaunchKernelGGL(k_codes, dim3(u256), dim3(256), 0, s, canon, stride, U, C, code, hist);
+  scan_exclusive(s, hist, boff, ncode + 1, scr2);
+  hipLaunchKernelGGL(k_bucket_scatter, dim3(u256), dim3(256), 0, s, code, U, boff, cur, bl);
+  hipLaunchKernelGGL(k_pairs_bucket, dim3(u256), dim3(256), 0, s, canon, stride, n, U, W, mskb, lo, boff, bl, C,
+                     alive);
   scan_exclusive(s, alive, pos, U, scr);
   hipMemcpyAsync(&hlast[0], pos + U - 1, 4, hipMemcpyDeviceToHost, s);
   hipMemcpyAsync(&hlast[1], alive + U - 1, 4, hipMemcpyDeviceToHost, s);

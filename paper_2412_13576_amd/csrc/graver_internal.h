@@ -12,7 +12,7 @@
 struct graver_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
-  static constexpr int kSlots = 40;
+  static constexpr int kSlots = 48;
   void* buf[kSlots] = {};
   size_t cap[kSlots] = {};
   void* host_pinned = nullptr;  // small pinned staging area
@@ -32,6 +32,7 @@ enum Slot : int {
   WS_F_CANON, WS_F_UNIQ, WS_F_L1, WS_F_MASK, WS_F_LO, WS_F_ALIVE, WS_F_OUT,
   WS_A_R, WS_A_PART, WS_A_DONE, WS_A_QG, WS_A_TAB, WS_A_PX, WS_A_STEPS,
   WS_MF_B, WS_MF_BT, WS_MF_STATE, WS_MISC,
+  WS_F_CODE, WS_F_HIST, WS_F_OFF, WS_F_CUR, WS_F_BL, WS_A_QFLAG,
 };
 void* ws_get(graver_ctx* ctx, int slot, size_t bytes, graver_status* st);
 
@@ -83,7 +84,7 @@ hipError_t launch_f32_state_io(hipStream_t s, int n, int d, int64_t N, float* st
 
 hipError_t launch_pool_clear(hipStream_t s, PoolDev p);
 hipError_t launch_verify(hipStream_t s, PoolDev p, uint32_t count, int m, const int64_t* A,
-                         unsigned int* bad);
+                         unsigned int* bad, int a_small);
 hipError_t launch_sort_keys(hipStream_t s, const int8_t* keys, int stride, int n, uint32_t count,
                             uint32_t* idx, uint32_t* tmp, int by_l1, const int32_t* l1);
 hipError_t launch_gather_keys(hipStream_t s, const int8_t* keys, int stride, int n,

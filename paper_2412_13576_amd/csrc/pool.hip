@@ -22,16 +22,33 @@ hipError_t launch_pool_clear(hipStream_t s, PoolDev p) {
   return hipGetLastError();
 }
 
-// One thread per key: every row of A must annihilate the key exactly.
+// One thread per key: every row of A must annihilate the key exactly
+// (condition C1).  A is staged in LDS as int32 when every |A_ij| < 2^23, so
+// each row sum is below 2^23 * 127 * n < 2^63 in int64 accumulation; the key
+// is read four bytes at a time.
 __global__ void k_verify(const int8_t* keys, int stride, int n, uint32_t count, int m,
-                         const int64_t* __restrict__ A, unsigned int* bad) {
+                         const int64_t* __restrict__ A, unsigned int* bad, int use_lds) {
+  extern __shared__ int32_t sA[];
+  if (use_lds) {
+    for (int t = threadIdx.x; t < m * n; t += blockDim.x) sA[t] = (int32_t)A[t];
+    __syncthreads();
+  }
   uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= count) return;
-  const int8_t* g = keys + (size_t)k * stride;
+  const uint32_t* g4 = reinterpret_cast<const uint32_t*>(keys + (size_t)k * stride);
+  const int nw = (n + 3) / 4;
   for (int i = 0; i < m; ++i) {
     int64_t s = 0;
-    const int64_t* a = A + (size_t)i * n;
-    for (int j = 0; j < n; ++j) s += a[j] * (int64_t)g[j];
+    for (int w = 0; w < nw; ++w) {
+      uint32_t word = g4[w];
+      for (int b = 0; b < 4; ++b) {
+        int j = 4 * w + b;
+        if (j >= n) break;
+        int gv = (int8_t)(word >> (8 * b));
+        int64_t av = use_lds ? (int64_t)sA[i * n + j] : A[(size_t)i * n + j];
+        s += av * gv;
+      }
+    }
     if (s != 0) {
       atomicAdd(bad, 1u);
       return;
@@ -40,12 +57,14 @@ __global__ void k_verify(const int8_t* keys, int stride, int n, uint32_t count, 
 }
 
 hipError_t launch_verify(hipStream_t s, PoolDev p, uint32_t count, int m, const int64_t* A,
-                         unsigned int* bad) {
+                         unsigned int* bad, int a_small) {
   hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, reinterpret_cast<uint64_t*>(bad),
                      (uint64_t)1, (uint64_t)0);
   if (count == 0) return hipGetLastError();
-  hipLaunchKernelGGL(k_verify, dim3((count + 255) / 256), dim3(256), 0, s, p.keys, p.stride, p.n,
-                     count, m, A, bad);
+  size_t lds = (size_t)m * p.n * sizeof(int32_t);
+  int use_lds = a_small && lds <= 48 * 1024;
+  hipLaunchKernelGGL(k_verify, dim3((count + 255) / 256), dim3(256), use_lds ? lds : 0, s, p.keys, p.stride,
+                     p.n, count, m, A, bad, use_lds);
   return hipGetLastError();
 }
 

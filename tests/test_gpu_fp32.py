@@ -246,3 +246,33 @@ def test_fp32_resume_is_exact(G, ctx, qp):
     st2 = {"z": z0.clone(), "m": torch.zeros_like(z0), "v": torch.zeros_like(z0)}
     G.extract(ctx, prob, G.extract_params(N, 120, precision=G.GRAVER_FP32, init_mode=1, collect=0), state=st2)
     assert torch.equal(st1["z"], st2["z"]) and torch.equal(st1["v"], st2["v"])
+
+
+def test_full_size_filter_sampled(G, ctx, qp):
+    """Minimality filter on the full-size binary32 extraction: sampled
+    survivors have no witness in the input, sampled removed keys have one,
+    and the output is canonical, sorted and a subset of the input."""
+    from oracle.conformal import canonical
+    from oracle.minimal import has_witness
+    inst, B, P = qp
+    N, T = 65536, 2000
+    _say("full size filter", N, T)
+    prob = G.DeviceProblem.from_numpy(inst.A, inst.b, inst.l, inst.u, B, P)
+    prm = G.extract_params(N, T, precision=G.GRAVER_FP32, init_mode=0, seed=77, pool_capacity=1 << 23)
+    keys, _ = G.extract(ctx, prob, prm)
+    out = G.filter_minimal(ctx, keys)
+    X = keys.cpu().numpy().astype(np.int64)
+    Y = out.cpu().numpy().astype(np.int64)
+    Cin = np.array(sorted({canonical(r) for r in X}), dtype=np.int64)
+    rows = [tuple(r) for r in Y]
+    assert rows == sorted(rows) and all(r == canonical(r) for r in rows[:5000])
+    cin = {tuple(r) for r in Cin}
+    assert all(r in cin for r in rows)
+    kept = set(rows)
+    removed = [r for r in cin if r not in kept]
+    _say("full size filter", "in", len(cin), "out", len(rows), "removed", len(removed))
+    rng = np.random.default_rng(1)
+    for i in rng.choice(len(rows), size=12, replace=False):
+        assert not has_witness(Cin, rows[i])
+    for i in rng.permutation(len(removed))[:12]:
+        assert has_witness(Cin, removed[i])

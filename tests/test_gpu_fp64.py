@@ -171,6 +171,14 @@ def _filter_cases():
         X[::7] = X[::7] * 2
         cases.append((f"random-n{n}", X.astype(np.int8)))
     cases.append(("single", np.array([[0, -3, 1]], dtype=np.int8)))
+    # dense keys (the shape the QP workload produces) and a structured set in
+    # which many keys have witnesses: both exercise the sign-pattern index
+    D = rng.integers(-12, 13, size=(2500, 100))
+    D[rng.random(D.shape) < 0.09] = 0
+    cases.append(("dense-n100", D.astype(np.int8)))
+    base = rng.integers(-2, 3, size=(600, 20)) * (rng.random((600, 20)) < 0.4)
+    mult = base[rng.integers(0, 600, size=3000)] + base[rng.integers(0, 600, size=3000)]
+    cases.append(("sums-n20", np.concatenate([base, mult]).astype(np.int8)))
     return cases
 
 
