@@ -187,8 +187,9 @@ graver_status graver_extract(graver_ctx* ctx, const graver_problem* prob,
   const int T = prm->iters;
   if (d < 1 || d > n || !prob->B) return set_error(GRAVER_E_INVALID, "need a basis B with 1 <= d <= n");
   if (N < 1 || N > (int64_t)1 << 30 || T < 0) return set_error(GRAVER_E_INVALID, "bad n_starts / iters");
-  if (prm->precision != GRAVER_FP64 && prm->precision != GRAVER_FP32)
-    return set_error(GRAVER_E_INVALID, "precision not available");
+  if (prm->precision != GRAVER_FP64 && prm->precision != GRAVER_FP32 && prm->precision != GRAVER_BF16)
+    return set_error(GRAVER_E_INVALID, "unknown precision");
+  if (prm->polish_iters < 0) return set_error(GRAVER_E_INVALID, "polish_iters < 0");
   if (prm->init_mode == 0 && !prob->P) return set_error(GRAVER_E_INVALID, "init_mode 0 needs P");
   if (prm->init_mode == 1 && (!state || !state->z))
     return set_error(GRAVER_E_INVALID, "init_mode 1 needs state->z");
@@ -300,6 +301,7 @@ graver_status graver_extract(graver_ctx* ctx, const graver_problem* prob,
   da.one_minus_b2 = 1.0 - prm->beta2;
   da.bc = dbc;
   da.collect = prm->collect;
+  da.bf16_iters = prm->precision == GRAVER_BF16 ? std::max(0, T - prm->polish_iters) : 0;
 
   {
     if (prm->precision == GRAVER_FP64) {
@@ -315,7 +317,7 @@ graver_status graver_extract(graver_ctx* ctx, const graver_problem* prob,
       stt.ms_descent = tm.stop_ms();
     } else {
       if (!descent_f32_supported(n, d))
-        return set_error(GRAVER_E_INVALID, "FP32 descent supports n <= 128, d <= 128 in this build");
+        return set_error(GRAVER_E_INVALID, "the MFMA descent supports n <= 128, d <= 128 in this build");
       float* Bp = (float*)ws_get(ctx, WS_MF_B, f32_pack_floats(n, d) * sizeof(float), &st);
       if (!Bp) return st;
       float* BTp = (float*)ws_get(ctx, WS_MF_BT, f32_pack_floats(n, d) * sizeof(float), &st);
@@ -325,10 +327,12 @@ graver_status graver_extract(graver_ctx* ctx, const graver_problem* prob,
       float* fstate = (float*)ws_get(ctx, WS_MF_STATE, f32_state_floats(n, d, N) * sizeof(float), &st);
       if (!fstate) return st;
       HIP_TRY(launch_f32_pack(s, n, d, prob->B, Bp, BTp, rowl1), "pack basis");
-      int hrow = 0;
-      HIP_TRY(hipMemcpyAsync(&hrow, rowl1, sizeof(int), hipMemcpyDeviceToHost, s), "row l1");
+      int hrow[2] = {0, 0};
+      HIP_TRY(hipMemcpyAsync(hrow, rowl1, 2 * sizeof(int), hipMemcpyDeviceToHost, s), "row l1");
       HIP_TRY(hipStreamSynchronize(s), "sync");
-      float zrange = (float)std::min(1073741824.0, std::floor(16777216.0 / std::max(hrow, 1)));
+      if (hrow[1] > 256)
+        return set_error(GRAVER_E_INVALID, "the MFMA descent needs |B_ij| <= 256 (exact bf16 operands)");
+      float zrange = (float)std::min(1073741824.0, std::floor(16777216.0 / std::max(hrow[0], 1)));
       HIP_TRY(launch_f32_state_io(s, n, d, N, fstate, z, mm, vv, 1), "state in");
       EventTimer tm(s);
       if (T > 0)

@@ -2,8 +2,8 @@
 // gfx950 matrix cores.
 //
 // One wave owns 16 starts for the whole call; their z, m, v stay in
-// registers.  Both contractions run on v_mfma_f32_16x16x4_f32 in transposed
-// form so that no data moves between them:
+// registers.  Both contractions run on matrix cores in transposed form so
+// that no data moves between them:
 //   forward   Y^T (n x 16) = B   (n x d) * Z^T (d x 16)
 //   backward  G^T (d x 16) = B^T (d x n) * sign(Y)^T (n x 16)
 // In a 16x16x4 MFMA, lane l supplies A[l%16][l/16] and B[l/16][l%16] and
@@ -11,8 +11,17 @@
 // MFMA of a 16-block mapped to rows 4k+r, the forward result held by lane l
 // (rows 4*(l/16)+r of start l%16) is exactly the backward B operand it
 // must supply, and the backward result has the layout of z.  The A
-// operands (entries of B) come from LDS, pre-packed so each lane reads one
-// float4 per 16x16 block.
+// operands (entries of B) come from LDS, pre-packed per 16x16 block.
+//
+// Backward: sign(y) is in {-1, 0, 1} and the entries of B are small
+// integers (|B_ij| <= 256, checked by the host), so bf16 operands are exact
+// and the fp32 sums are exact integers: v_mfma_f32_16x16x16_bf16 gives the
+// same result as binary32 arithmetic.  Its 4-value K group per lane is one
+// 16-row block, so the forward accumulator of block ib is the operand.
+// Forward: binary32 (v_mfma_f32_16x16x4_f32) in FP32 mode; in BF16 mode
+// z = hi + lo with hi = bf16(z), lo = bf16(z - hi) and B z = B hi + B lo on
+// v_mfma_f32_16x16x16_bf16 (products exact, fp32 accumulation), except the
+// last polish iterations, which use the binary32 forward.
 //
 // After the Adam step every coordinate is rounded (ties to even).  The
 // exact candidate g = B r of every start is tracked incrementally:
@@ -31,6 +40,7 @@
 namespace graver {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef short shortx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kWavesPerBlock = 4;
 constexpr int kMaxBlk = 8;  // n, d <= 128
@@ -39,7 +49,8 @@ bool descent_f32_supported(int n, int d) { return n <= 16 * kMaxBlk && d <= 16 *
 
 static inline int blk(int x) { return (x + 15) / 16; }
 
-size_t f32_pack_floats(int n, int d) { return (size_t)blk(n) * blk(d) * 64 * 4; }
+// FA (float4 per lane and block) followed by FB (4 bf16 per lane and block).
+size_t f32_pack_floats(int n, int d) { return (size_t)blk(n) * blk(d) * 64 * 6; }
 
 static inline int64_t n_waves(int64_t N) {
   int64_t w = (N + 15) / 16;
@@ -51,9 +62,16 @@ size_t f32_state_floats(int n, int d, int64_t N) {
   return 3 * (size_t)n_waves(N) * 4 * blk(d) * 64;
 }
 
-// FA[(ib*DB + jb)*64 + l] = (B[16ib + l%16][16jb + 4(l/16) + r], r = 0..3)
-// BA[(jb*NB + ib)*64 + l] = (B[16ib + 4(l/16) + r][16jb + l%16], r = 0..3)
-__global__ void k_pack(int n, int d, int NB, int DB, const int64_t* B, float* FA, float* BA) {
+// FA[(ib*DB + jb)*64 + l] = (B[16ib + l%16][16jb + 4(l/16) + r], r = 0..3)      float
+// FB[(ib*DB + jb)*64 + l] = the same four entries                              bf16
+// BT[(jb*NB + ib)*64 + l] = (B[16ib + 4(l/16) + r][16jb + l%16], r = 0..3)      bf16
+__device__ __forceinline__ short bf16_bits_exact_int(int64_t v) {
+  // v is an integer with |v| <= 256: exactly representable in bf16
+  float f = (float)v;
+  return (short)(__float_as_uint(f) >> 16);
+}
+
+__global__ void k_pack(int n, int d, int NB, int DB, const int64_t* B, float* FA, short* FB, short* BT) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   int total = NB * DB * 64;
   if (t >= total) return;
@@ -63,7 +81,9 @@ __global__ void k_pack(int n, int d, int NB, int DB, const int64_t* B, float* FA
     int i = 16 * ib + l % 16;
     for (int r = 0; r < 4; ++r) {
       int j = 16 * jb + 4 * (l / 16) + r;
-      FA[(size_t)t * 4 + r] = (i < n && j < d) ? (float)B[(size_t)i * d + j] : 0.f;
+      int64_t b = (i < n && j < d) ? B[(size_t)i * d + j] : 0;
+      FA[(size_t)t * 4 + r] = (float)b;
+      FB[(size_t)t * 4 + r] = bf16_bits_exact_int(b);
     }
   }
   {
@@ -71,35 +91,48 @@ __global__ void k_pack(int n, int d, int NB, int DB, const int64_t* B, float* FA
     int j = 16 * jb + l % 16;
     for (int r = 0; r < 4; ++r) {
       int i = 16 * ib + 4 * (l / 16) + r;
-      BA[(size_t)t * 4 + r] = (i < n && j < d) ? (float)B[(size_t)i * d + j] : 0.f;
+      int64_t b = (i < n && j < d) ? B[(size_t)i * d + j] : 0;
+      BT[(size_t)t * 4 + r] = bf16_bits_exact_int(b);
     }
   }
 }
 
+// out[0] = max_i sum_j |B_ij|, out[1] = max |B_ij| (both clamped to 2^30)
 __global__ void k_rowl1(int n, int d, const int64_t* B, int* out) {
-  __shared__ int sh[256];
-  int best = 0;
+  __shared__ int sh[256], sm[256];
+  int best = 0, bmax = 0;
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     int64_t s = 0;
     for (int j = 0; j < d; ++j) {
       int64_t b = B[(size_t)i * d + j];
-      s += b < 0 ? -b : b;
+      b = b < 0 ? -b : b;
+      s += b;
+      bmax = max(bmax, (int)min<int64_t>(b, 1 << 30));
     }
     best = max(best, (int)min<int64_t>(s, 1 << 30));
   }
   sh[threadIdx.x] = best;
+  sm[threadIdx.x] = bmax;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) sh[threadIdx.x] = max(sh[threadIdx.x], sh[threadIdx.x + o]);
+    if ((int)threadIdx.x < o) {
+      sh[threadIdx.x] = max(sh[threadIdx.x], sh[threadIdx.x + o]);
+      sm[threadIdx.x] = max(sm[threadIdx.x], sm[threadIdx.x + o]);
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) *out = sh[0];
+  if (threadIdx.x == 0) {
+    out[0] = sh[0];
+    out[1] = sm[0];
+  }
 }
 
 hipError_t launch_f32_pack(hipStream_t s, int n, int d, const int64_t* B, float* Bp, float* BTp, int* rowl1) {
   int NB = blk(n), DB = blk(d);
   int total = NB * DB * 64;
-  hipLaunchKernelGGL(k_pack, dim3((total + 255) / 256), dim3(256), 0, s, n, d, NB, DB, B, Bp, BTp);
+  short* FB = reinterpret_cast<short*>(Bp + (size_t)total * 4);
+  hipLaunchKernelGGL(k_pack, dim3((total + 255) / 256), dim3(256), 0, s, n, d, NB, DB, B, Bp, FB,
+                     reinterpret_cast<short*>(BTp));
   hipLaunchKernelGGL(k_rowl1, dim3(1), dim3(256), 0, s, n, d, B, rowl1);
   return hipGetLastError();
 }
@@ -162,22 +195,35 @@ __device__ __forceinline__ int xand4(int x) {
   return x & __shfl_xor(x, 32, 64);
 }
 
+__device__ __forceinline__ short bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f(short h) { return __uint_as_float((uint32_t)(uint16_t)h << 16); }
+__device__ __forceinline__ short sign_bf16(float y) {
+  return y > 0.f ? (short)0x3F80 : (y < 0.f ? (short)0xBF80 : (short)0);
+}
+
 template <int NB, int DB>
 __global__ __launch_bounds__(64 * kWavesPerBlock, 2) void k_descent_f32(DescentArgs a, const floatx4* __restrict__ FA,
-                                                                         const floatx4* __restrict__ BA,
+                                                                         const shortx4* __restrict__ FB,
+                                                                         const shortx4* __restrict__ BT,
                                                                          float* __restrict__ state, PoolDev pool,
                                                                          unsigned long long* counters,
                                                                          float zrange, int64_t per) {
   extern __shared__ __align__(16) unsigned char smem[];
   floatx4* sFA = reinterpret_cast<floatx4*>(smem);
-  floatx4* sBA = sFA + NB * DB * 64;
-  int* sLim = reinterpret_cast<int*>(sBA + NB * DB * 64);
+  shortx4* sFB = reinterpret_cast<shortx4*>(sFA + NB * DB * 64);
+  shortx4* sBT = sFB + NB * DB * 64;
+  int* sLim = reinterpret_cast<int*>(sBT + NB * DB * 64);
   int8_t* sKeys = reinterpret_cast<int8_t*>(sLim + 16 * NB);
   const int stride = pool.stride;
 
   for (int t = threadIdx.x; t < NB * DB * 64; t += blockDim.x) {
     sFA[t] = FA[t];
-    sBA[t] = BA[t];
+    sFB[t] = FB[t];
+    sBT[t] = BT[t];
   }
   for (int i = threadIdx.x; i < 16 * NB; i += blockDim.x)
     sLim[i] = i < a.n ? (int)(a.u[i] - a.l[i]) : 0;
@@ -220,35 +266,48 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 2) void k_descent_f32(DescentA
     floatx4 acc[NB];
 #pragma unroll
     for (int ib = 0; ib < NB; ++ib) acc[ib] = floatx4{0.f, 0.f, 0.f, 0.f};
+    if (k < a.bf16_iters) {
 #pragma unroll
-    for (int jb = 0; jb < DB; ++jb) {
-      floatx4 A[NB];
+      for (int jb = 0; jb < DB; ++jb) {
+        shortx4 hi, lo;
 #pragma unroll
-      for (int ib = 0; ib < NB; ++ib) A[ib] = sFA[(ib * DB + jb) * 64 + lane];
+        for (int r = 0; r < 4; ++r) {
+          short h = bf16_rne(z[jb][r]);
+          hi[r] = h;
+          lo[r] = bf16_rne(z[jb][r] - bf16_to_f(h));
+        }
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
+        for (int ib = 0; ib < NB; ++ib) {
+          const shortx4 A = sFB[(ib * DB + jb) * 64 + lane];
+          acc[ib] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, hi, acc[ib], 0, 0, 0);
+          acc[ib] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, lo, acc[ib], 0, 0, 0);
+        }
+      }
+    } else {
 #pragma unroll
-        for (int ib = 0; ib < NB; ++ib)
-          acc[ib] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[ib][r], z[jb][r], acc[ib], 0, 0, 0);
+      for (int jb = 0; jb < DB; ++jb) {
+        floatx4 A[NB];
+#pragma unroll
+        for (int ib = 0; ib < NB; ++ib) A[ib] = sFA[(ib * DB + jb) * 64 + lane];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int ib = 0; ib < NB; ++ib)
+            acc[ib] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[ib][r], z[jb][r], acc[ib], 0, 0, 0);
+      }
     }
-#pragma unroll
-    for (int ib = 0; ib < NB; ++ib)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) acc[ib][r] = sgnf(acc[ib][r]);
-    // ---- backward G^T = B^T sign(Y)^T ----
+    // ---- backward G^T = B^T sign(Y)^T on exact bf16 operands ----
     floatx4 gacc[DB];
 #pragma unroll
     for (int jb = 0; jb < DB; ++jb) gacc[jb] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int ib = 0; ib < NB; ++ib) {
-      floatx4 A[DB];
+      shortx4 sg;
 #pragma unroll
-      for (int jb = 0; jb < DB; ++jb) A[jb] = sBA[(jb * NB + ib) * 64 + lane];
+      for (int r = 0; r < 4; ++r) sg[r] = sign_bf16(acc[ib][r]);
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int jb = 0; jb < DB; ++jb)
-          gacc[jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[jb][r], acc[ib][r], gacc[jb], 0, 0, 0);
+      for (int jb = 0; jb < DB; ++jb)
+        gacc[jb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(sBT[(jb * NB + ib) * 64 + lane], sg, gacc[jb], 0, 0, 0);
     }
     // ---- barrier term: ||z||_inf and ties, per start (4 lanes) ----
     float mu = 0.f;
@@ -390,14 +449,15 @@ static hipError_t launch_nd(hipStream_t s, const DescentArgs& a, const float* FA
                             PoolDev pool, unsigned long long* counters, float zrange) {
   const int64_t nw = n_waves(a.N);
   const int64_t per = nw * 4 * DB * 64;
-  const size_t shmem = (size_t)2 * NB * DB * 64 * sizeof(floatx4) + 16 * NB * sizeof(int) +
+  const size_t shmem = (size_t)NB * DB * 64 * (sizeof(floatx4) + 2 * sizeof(shortx4)) + 16 * NB * sizeof(int) +
                        (size_t)kWavesPerBlock * 16 * pool.stride;
   auto kern = k_descent_f32<NB, DB>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
   if (e != hipSuccess) return e;
+  const size_t nblk64 = (size_t)NB * DB * 64;
   hipLaunchKernelGGL(kern, dim3((unsigned)(nw / kWavesPerBlock)), dim3(64 * kWavesPerBlock), shmem, s, a,
-                     reinterpret_cast<const floatx4*>(FA), reinterpret_cast<const floatx4*>(BA), state, pool,
-                     counters, zrange, per);
+                     reinterpret_cast<const floatx4*>(FA), reinterpret_cast<const shortx4*>(FA + nblk64 * 4),
+                     reinterpret_cast<const shortx4*>(BA), state, pool, counters, zrange, per);
   return hipGetLastError();
 }
 

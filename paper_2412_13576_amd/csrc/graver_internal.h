@@ -63,6 +63,7 @@ struct DescentArgs {
   double one_minus_b1, one_minus_b2;
   const double* bc;     // 2*T bias corrections (device): [2k] = 1-b1^t, [2k+1] = 1-b2^t
   int32_t collect;
+  int32_t bf16_iters;   // MFMA path: iterations k < bf16_iters use the bf16 hi/lo forward
 };
 
 hipError_t launch_init_box(hipStream_t s, int n, int d, int64_t N, const double* P,

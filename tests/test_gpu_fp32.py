@@ -276,3 +276,65 @@ def test_full_size_filter_sampled(G, ctx, qp):
         assert not has_witness(Cin, rows[i])
     for i in rng.permutation(len(removed))[:12]:
         assert has_witness(Cin, removed[i])
+
+
+@pytest.mark.parametrize("t_teacher", [0, 99, 1999])
+def test_teacher_forced_single_step_bf16(G, ctx, qp, t_teacher):
+    """BF16 form (hi/lo split forward on bf16 matrix cores, exact bf16
+    backward, binary32 Adam): one step from oracle states within 2e-3."""
+    inst, B, P = qp
+    _say("teacher-forced bf16", t_teacher)
+    N = 128
+    _, z0 = philox.box_starts(P, inst.l, inst.u, N, seed=23)
+    z, m, v, _ = S.descend(B, z0, t_teacher, P_) if t_teacher else (z0, np.zeros_like(z0), np.zeros_like(z0), 0)
+    zo, mo, vo, _ = S.descend(B, z, 1, P_, m0=m, v0=v, t0=t_teacher)
+    prob = G.DeviceProblem.from_numpy(inst.A, inst.b, inst.l, inst.u, B)
+    st = {"z": _dev(z), "m": _dev(m), "v": _dev(v)}
+    prm = G.extract_params(N, 1, precision=G.GRAVER_BF16, init_mode=1, t0=t_teacher, collect=0)
+    G.extract(ctx, prob, prm, state=st)
+    err, flagged = _check_step(B, z, m, v, t_teacher + 1, st["z"].cpu().numpy(), zo)
+    _say("teacher-forced bf16", t_teacher, "max err", float(err.max()), "kink-branch starts", flagged)
+
+
+def test_bf16_with_full_polish_equals_fp32(G, ctx, qp):
+    """With polish_iters >= iters every step uses the binary32 forward, so the
+    BF16 form reproduces the FP32 form bit for bit."""
+    inst, B, P = qp
+    _say("bf16 full polish == fp32")
+    N = 2048
+    prob = G.DeviceProblem.from_numpy(inst.A, inst.b, inst.l, inst.u, B, P)
+    outs = []
+    for prec, pol in ((G.GRAVER_FP32, 0), (G.GRAVER_BF16, 50)):
+        st = {"z": torch.zeros((N, B.shape[1]), dtype=torch.float64, device="cuda"),
+              "m": torch.zeros((N, B.shape[1]), dtype=torch.float64, device="cuda")}
+        prm = G.extract_params(N, 50, precision=prec, init_mode=0, seed=8, polish_iters=pol,
+                               pool_capacity=1 << 20)
+        k, _ = G.extract(ctx, prob, prm, state=st)
+        outs.append((st["z"].clone(), k.clone()))
+    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+
+
+def test_precision_forms_recall(G, ctx, qp):
+    """FP32 vs BF16 (last 10% of the steps polished in binary32) on 16384
+    starts x 2000 steps: extracted-direction recall against the filtered
+    union of both sets (the comparison of the precision form)."""
+    inst, B, P = qp
+    N, T = 16384, 2000
+    _say("precision recall", N, T)
+    prob = G.DeviceProblem.from_numpy(inst.A, inst.b, inst.l, inst.u, B, P)
+    sets, times = {}, {}
+    for name, prec, pol in (("fp32", G.GRAVER_FP32, 0), ("bf16", G.GRAVER_BF16, T // 10)):
+        prm = G.extract_params(N, T, precision=prec, init_mode=0, seed=4242, polish_iters=pol,
+                               pool_capacity=1 << 22)
+        k, st = G.extract(ctx, prob, prm)
+        sets[name] = k
+        times[name] = st["ms_descent"]
+    ref = G.filter_minimal(ctx, torch.cat([sets["fp32"], sets["bf16"]]))
+    R = {tuple(r) for r in ref.cpu().numpy().tolist()}
+    from oracle.conformal import canonical
+    rec = {}
+    for name, k in sets.items():
+        C = {canonical(r) for r in k.cpu().numpy().tolist()}
+        rec[name] = len(C & R) / len(R)
+    _say("precision recall", rec, "descent ms", times)
+    assert rec["bf16"] >= rec["fp32"] - 0.05
