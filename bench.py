@@ -57,6 +57,8 @@ def main():
     ap.add_argument("--starts", type=int, default=65536)
     ap.add_argument("--iters", type=int, default=2000)
     ap.add_argument("--aug-starts", type=int, default=200)
+    ap.add_argument("--precision", choices=["fp32", "bf16"], default="fp32")
+    ap.add_argument("--polish", type=int, default=200, help="bf16: final iterations in binary32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -82,8 +84,9 @@ def main():
     keys_buf_cap = pool_cap
 
     def step(seed):
-        prm = G.extract_params(N, T, precision=G.GRAVER_FP32, init_mode=0, seed=seed,
-                               pool_capacity=pool_cap)
+        prec = G.GRAVER_FP32 if args.precision == "fp32" else G.GRAVER_BF16
+        prm = G.extract_params(N, T, precision=prec, init_mode=0, seed=seed, pool_capacity=pool_cap,
+                               polish_iters=args.polish if args.precision == "bf16" else 0)
         keys, st = G.extract(ctx, prob, prm, keys_cap=keys_buf_cap)
         F = G.filter_minimal(ctx, keys)
         x, f, steps, best = G.augment(ctx, prob, obj, F, starts)
@@ -116,11 +119,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if args.precision == "fp32" else "bf16+f32",
         "data": "synthetic",
         "config": {"workload": "qp_m20_n100: m=20, n=100 (d=80), A in {-1,0,1} density 0.3, "
                                "nonconvex dense quadratic f, box [-10,10]",
-                   "starts": N, "iters": T, "aug_starts": S0, "precision": "fp32-mfma"},
+                   "starts": N, "iters": T, "aug_starts": S0,
+                   "precision": "fp32-mfma" if args.precision == "fp32" else f"bf16-mfma, {args.polish} fp32 polish"},
         "verified_directions_per_s": float(np.mean(n_keys)) / (ms_step * 1e-3),
         "descent_start_iterations_per_s": N * T / (desc_ms * 1e-3),
         "extract": {k: float(np.mean([r[2][k] for r in recs])) for k in

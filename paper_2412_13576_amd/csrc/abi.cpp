@@ -302,6 +302,9 @@ graver_status graver_extract(graver_ctx* ctx, const graver_problem* prob,
   da.bc = dbc;
   da.collect = prm->collect;
   da.bf16_iters = prm->precision == GRAVER_BF16 ? std::max(0, T - prm->polish_iters) : 0;
+  da.lim_uniform = (int32_t)(hu[0] - hl[0]);
+  for (int i = 1; i < n; ++i)
+    if (hu[i] - hl[i] != hu[0] - hl[0]) da.lim_uniform = -1;
 
   {
     if (prm->precision == GRAVER_FP64) {
@@ -334,10 +337,20 @@ graver_status graver_extract(graver_ctx* ctx, const graver_problem* prob,
         return set_error(GRAVER_E_INVALID, "the MFMA descent needs |B_ij| <= 256 (exact bf16 operands)");
       float zrange = (float)std::min(1073741824.0, std::floor(16777216.0 / std::max(hrow[0], 1)));
       HIP_TRY(launch_f32_state_io(s, n, d, N, fstate, z, mm, vv, 1), "state in");
+      LogDev lg{};
+      lg.stride = pool.stride;
+      lg.cap = prm->collect ? pool.cap : 0u;
+      lg.rows = (int8_t*)ws_get(ctx, WS_LOG, (size_t)std::max<uint32_t>(lg.cap, 1) * pool.stride, &st);
+      if (!lg.rows) return st;
+      lg.count = (uint32_t*)ws_get(ctx, WS_LOG_COUNT, 64, &st);
+      if (!lg.count) return st;
+      HIP_TRY(hipMemsetAsync(lg.count, 0, 64, s), "clear log count");
+      da.log = lg;
       EventTimer tm(s);
       if (T > 0)
         HIP_TRY(launch_descent_f32(s, da, Bp, BTp, fstate, pool, counters, zrange), "descent fp32");
       stt.ms_descent = tm.stop_ms();
+      if (prm->collect && T > 0) HIP_TRY(launch_log_insert(s, lg, pool), "log insert");
       HIP_TRY(launch_f32_state_io(s, n, d, N, fstate, z, mm, vv, 0), "state out");
     }
   }

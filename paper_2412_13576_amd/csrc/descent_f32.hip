@@ -205,13 +205,23 @@ __device__ __forceinline__ short sign_bf16(float y) {
   return y > 0.f ? (short)0x3F80 : (y < 0.f ? (short)0xBF80 : (short)0);
 }
 
+constexpr int kLogChunk = 64;
+
+// Zero `rows` consecutive log rows starting at `first` with the 64 lanes.
+__device__ __forceinline__ void zero_rows(const LogDev& log, uint32_t first, uint32_t rows, int lane) {
+  const int dw = log.stride / 4;
+  uint32_t* base = reinterpret_cast<uint32_t*>(log.rows + (size_t)first * log.stride);
+  for (uint32_t t = lane; t < rows * (uint32_t)dw; t += 64) base[t] = 0u;
+}
+
 template <int NB, int DB>
 __global__ __launch_bounds__(64 * kWavesPerBlock, 2) void k_descent_f32(DescentArgs a, const floatx4* __restrict__ FA,
                                                                          const shortx4* __restrict__ FB,
                                                                          const shortx4* __restrict__ BT,
                                                                          float* __restrict__ state, PoolDev pool,
                                                                          unsigned long long* counters,
-                                                                         float zrange, int64_t per) {
+                                                                         float zrange, int64_t per,
+                                                                         int lim_uniform, LogDev log) {
   extern __shared__ __align__(16) unsigned char smem[];
   floatx4* sFA = reinterpret_cast<floatx4*>(smem);
   shortx4* sFB = reinterpret_cast<shortx4*>(sFA + NB * DB * 64);
@@ -257,6 +267,8 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 2) void k_descent_f32(DescentA
 
   bool alive = svalid;
   unsigned long long n_emit = 0, n_inbox = 0, n_range = 0;
+  uint32_t lbase = 0, lused = 0;
+  int lleft = 0;
   const float lam1 = (float)a.lambda1, lam2 = (float)a.lambda2;
   const float b1 = (float)a.beta1, b2 = (float)a.beta2, omb1 = (float)a.one_minus_b1, omb2 = (float)a.one_minus_b2;
   const float eps = (float)a.eps;
@@ -359,21 +371,35 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 2) void k_descent_f32(DescentA
       for (int jb = 0; jb < DB; ++jb) dr[jb] = floatx4{0.f, 0.f, 0.f, 0.f};
     }
     const bool emit = alive && changed;
-    // ---- exact candidate update g += B (r - r_prev) on changed groups ----
+    // ---- exact candidate update g += B (r - r_prev) on changed blocks ----
+    // After the first step |r - r_prev| is small (an Adam step moves z by
+    // about lr), so the 4 differences of a block are exact bf16 operands; the
+    // first step (r_prev = 0) and any larger jump use the binary32 product.
     floatx4 dg[NB];
     bool any = false;
 #pragma unroll
     for (int ib = 0; ib < NB; ++ib) dg[ib] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int jb = 0; jb < DB; ++jb) {
+      const bool nz = (dr[jb][0] != 0.f) | (dr[jb][1] != 0.f) | (dr[jb][2] != 0.f) | (dr[jb][3] != 0.f);
+      if (__ballot(nz) == 0) continue;
+      any = true;
+      const bool small = fabsf(dr[jb][0]) <= 256.f && fabsf(dr[jb][1]) <= 256.f && fabsf(dr[jb][2]) <= 256.f &&
+                         fabsf(dr[jb][3]) <= 256.f;
+      if (k > 0 && __ballot(!small) == 0) {
+        shortx4 dp;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        if (__ballot(dr[jb][r] != 0.f) == 0) continue;
-        any = true;
+        for (int r = 0; r < 4; ++r) dp[r] = (short)(__float_as_uint(dr[jb][r]) >> 16);
 #pragma unroll
         for (int ib = 0; ib < NB; ++ib)
-          dg[ib] = __builtin_amdgcn_mfma_f32_16x16x4f32(sFA[(ib * DB + jb) * 64 + lane][r], dr[jb][r], dg[ib], 0,
-                                                         0, 0);
+          dg[ib] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(sFB[(ib * DB + jb) * 64 + lane], dp, dg[ib], 0, 0, 0);
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int ib = 0; ib < NB; ++ib)
+            dg[ib] = __builtin_amdgcn_mfma_f32_16x16x4f32(sFA[(ib * DB + jb) * 64 + lane][r], dr[jb][r], dg[ib], 0,
+                                                           0, 0);
       }
     }
     if (any) {
@@ -391,7 +417,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 2) void k_descent_f32(DescentA
       for (int r = 0; r < 4; ++r) {
         const int i = 16 * ib + 4 * q + r;
         const int g = gi[ib][r];
-        const int lim = sLim[i];
+        const int lim = lim_uniform >= 0 ? lim_uniform : sLim[i];
         inbox &= (g <= lim) & (g >= -lim);
         nonzero |= g != 0;
       }
@@ -400,7 +426,45 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 2) void k_descent_f32(DescentA
     const bool put = emit && inbox && nonzero;
     n_emit += (q == 0 && emit) ? 1 : 0;
     n_inbox += (q == 0 && put) ? 1 : 0;
-    if (__ballot(put) == 0) continue;
+    const uint64_t pm = __ballot(put && q == 0);  // bit s: start s of this wave logs a key
+    if (pm == 0) continue;
+    // ---- append the keys to the candidate log --------------------------
+    // Each lane holds rows 16ib + 4q .. +3 of its start's g: one dword per
+    // block.  Slots come from per-wave chunks of kLogChunk rows reserved with
+    // one atomic; unused slots are zeroed (the log reader skips zero rows).
+    const int npu = __popcll(pm);
+    if (npu > lleft) {
+      if (lleft > 0) {
+        zero_rows(log, lbase + lused, (uint32_t)lleft, lane);
+        lleft = 0;
+      }
+      uint32_t nb = 0;
+      if (lane == 0) nb = atomicAdd(log.count, (uint32_t)kLogChunk);
+      nb = __shfl(nb, 0, 64);
+      if (nb < log.cap) {
+        const uint32_t end = min(log.cap, nb + (uint32_t)kLogChunk);
+        lbase = nb;
+        lused = 0;
+        lleft = (int)(end - nb);
+      }
+    }
+    if (npu <= lleft) {
+      const uint32_t rank = (uint32_t)__popcll(pm & ((1ull << sl) - 1ull));
+      if (put) {
+        uint32_t* row = reinterpret_cast<uint32_t*>(log.rows + (size_t)(lbase + lused + rank) * stride);
+#pragma unroll
+        for (int ib = 0; ib < NB; ++ib) {
+          uint32_t w = 0;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) w |= ((uint32_t)(uint8_t)(int8_t)gi[ib][r]) << (8 * r);
+          row[4 * ib + q] = w;
+        }
+      }
+      lused += (uint32_t)npu;
+      lleft -= npu;
+      continue;
+    }
+    // ---- log exhausted: insert directly into the pool -------------------
     if (put) {
 #pragma unroll
       for (int ib = 0; ib < NB; ++ib)
@@ -422,6 +486,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 2) void k_descent_f32(DescentA
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
+  if (lleft > 0) zero_rows(log, lbase + lused, (uint32_t)lleft, lane);
 #pragma unroll
   for (int jb = 0; jb < DB; ++jb)
 #pragma unroll
@@ -447,6 +512,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 2) void k_descent_f32(DescentA
 template <int NB, int DB>
 static hipError_t launch_nd(hipStream_t s, const DescentArgs& a, const float* FA, const float* BA, float* state,
                             PoolDev pool, unsigned long long* counters, float zrange) {
+  const int lim_uniform = a.lim_uniform;
   const int64_t nw = n_waves(a.N);
   const int64_t per = nw * 4 * DB * 64;
   const size_t shmem = (size_t)NB * DB * 64 * (sizeof(floatx4) + 2 * sizeof(shortx4)) + 16 * NB * sizeof(int) +
@@ -457,7 +523,8 @@ static hipError_t launch_nd(hipStream_t s, const DescentArgs& a, const float* FA
   const size_t nblk64 = (size_t)NB * DB * 64;
   hipLaunchKernelGGL(kern, dim3((unsigned)(nw / kWavesPerBlock)), dim3(64 * kWavesPerBlock), shmem, s, a,
                      reinterpret_cast<const floatx4*>(FA), reinterpret_cast<const shortx4*>(FA + nblk64 * 4),
-                     reinterpret_cast<const shortx4*>(BA), state, pool, counters, zrange, per);
+                     reinterpret_cast<const shortx4*>(BA), state, pool, counters, zrange, per, lim_uniform,
+                     a.log);
   return hipGetLastError();
 }
 

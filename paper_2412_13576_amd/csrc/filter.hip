@@ -222,58 +222,97 @@ __global__ void k_bucket_scatter(const uint32_t* code, uint32_t count, const uin
   bl[off[cd] + atomicAdd(&cur[cd], 1u)] = p;
 }
 
-__global__ void k_pairs_bucket(const int8_t* keys, int stride, int n, uint32_t count, int W,
-                               const uint64_t* __restrict__ mask, const uint32_t* __restrict__ lo,
-                               const uint32_t* __restrict__ off, const uint32_t* __restrict__ bl, Coords C,
-                               uint32_t* alive) {
-  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= count) return;
-  const int8_t* g = keys + (size_t)p * stride;
-  const uint32_t my_lo = lo[p];
-  const uint64_t* gm = mask + (size_t)p * 2 * W;
-  bool dead = false;
-  if (my_lo > 0) {
+// Witness search as a tiled join over the sign-pattern index: block b owns
+// the keys g of bucket G = b (the positions bl[off[G] .. off[G+1]) ), one g
+// per thread.  The candidate buckets H (digits 0 or G's digit for "h below
+// g", 0 or the swapped digit for "-h below g") are the same for every g of
+// the block, so they are enumerated once per block and each is streamed
+// through LDS in tiles, every entry compared against every g of the chunk.
+constexpr int kJoinThreads = 256;
+
+__global__ __launch_bounds__(kJoinThreads) void k_pairs_join(const int8_t* keys, int stride, int n, int W,
+                                                           const uint64_t* __restrict__ mask,
+                                                           const uint32_t* __restrict__ lo,
+                                                           const uint32_t* __restrict__ off,
+                                                           const uint32_t* __restrict__ bl, Coords C, uint32_t ncode,
+                                                           int tile_n, uint32_t* alive) {
+  extern __shared__ uint64_t smem_join[];
+  uint64_t* tmask = smem_join;                                            // tile_n x 2W
+  uint32_t* tpos = reinterpret_cast<uint32_t*>(tmask + (size_t)tile_n * 2 * W);  // tile_n
+  __shared__ int any_alive;
+  for (uint32_t G = blockIdx.x; G < ncode; G += gridDim.x) {
+    const uint32_t gb = off[G], ge = off[G + 1];
+    if (gb == ge) continue;
     int cp[kMaxC], cn[kMaxC];
     int z = 0;
-    for (int i = 0; i < C.k; ++i) {
-      int v = g[C.c[i]];
-      if (v != 0) {
-        int dgt = v > 0 ? 1 : 2;
-        cp[z] = dgt * C.pow3[i];
-        cn[z] = (3 - dgt) * C.pow3[i];
-        ++z;
+    {
+      uint32_t rem = G;
+      for (int i = 0; i < C.k; ++i) {
+        int dgt = (int)(rem % 3u);
+        rem /= 3u;
+        if (dgt) {
+          cp[z] = dgt * C.pow3[i];
+          cn[z] = (3 - dgt) * C.pow3[i];
+          ++z;
+        }
       }
     }
     const uint32_t nsub = 1u << z;
-    for (int pol = 0; pol < 2 && !dead; ++pol) {
-      int code = 0;
-      for (uint32_t sidx = 0; sidx < nsub && !dead; ++sidx) {
-        if (sidx) {
-          int t = __builtin_ctz(sidx);
-          uint32_t gray = sidx ^ (sidx >> 1);
-          int cv = pol ? cn[t] : cp[t];
-          code += ((gray >> t) & 1u) ? cv : -cv;
-        }
-        const uint32_t e1 = off[code + 1];
-        for (uint32_t e = off[code]; e < e1; ++e) {
-          const uint32_t h = bl[e];
-          if (h >= my_lo) continue;
-          const uint64_t* hm = mask + (size_t)h * 2 * W;
-          bool ok = true;
-          for (int w = 0; w < W && ok; ++w) {
-            uint64_t hp = hm[w], hn = hm[W + w];
-            uint64_t gp = gm[w], gn = gm[W + w];
-            ok = pol ? ((hp & ~gn) | (hn & ~gp)) == 0 : ((hp & ~gp) | (hn & ~gn)) == 0;
+    for (uint32_t gc = gb; gc < ge; gc += kJoinThreads) {
+      const uint32_t e = gc + threadIdx.x;
+      const bool valid = e < ge;
+      const uint32_t p = valid ? bl[e] : 0u;
+      const uint32_t my_lo = valid ? lo[p] : 0u;
+      const int8_t* g = keys + (size_t)p * stride;
+      const uint64_t* gm = mask + (size_t)p * 2 * W;
+      uint64_t gp0 = valid ? gm[0] : 0ull, gn0 = valid ? gm[W] : 0ull;
+      const bool idle = !valid || my_lo == 0;  // nothing of smaller l1 to test
+      bool dead = false;
+      for (int pol = 0; pol < 2; ++pol) {
+        int code = 0;
+        for (uint32_t sidx = 0; sidx < nsub; ++sidx) {
+          if (sidx) {
+            int t = __builtin_ctz(sidx);
+            uint32_t gray = sidx ^ (sidx >> 1);
+            int cv = pol ? cn[t] : cp[t];
+            code += ((gray >> t) & 1u) ? cv : -cv;
           }
-          if (ok && magnitude_below(keys + (size_t)h * stride, g, n)) {
-            dead = true;
-            break;
+          const uint32_t hb = off[code], he = off[code + 1];
+          for (uint32_t t0 = hb; t0 < he; t0 += tile_n) {
+            __syncthreads();
+            if (threadIdx.x == 0) any_alive = 0;
+            __syncthreads();
+            if (!idle && !dead) any_alive = 1;
+            const uint32_t cnt = min((uint32_t)tile_n, he - t0);
+            for (uint32_t t = threadIdx.x; t < cnt; t += kJoinThreads) tpos[t] = bl[t0 + t];
+            __syncthreads();
+            if (!any_alive) continue;
+            for (uint32_t t = threadIdx.x; t < cnt * 2 * W; t += kJoinThreads) {
+              uint32_t ent = t / (2 * W), wd = t % (2 * W);
+              tmask[t] = mask[(size_t)tpos[ent] * 2 * W + wd];
+            }
+            __syncthreads();
+            if (idle || dead) continue;
+            for (uint32_t t = 0; t < cnt && !dead; ++t) {
+              const uint32_t h = tpos[t];
+              if (h >= my_lo) continue;
+              const uint64_t* hm = tmask + (size_t)t * 2 * W;
+              uint64_t hp = hm[0], hn = hm[W];
+              bool ok = pol ? ((hp & ~gn0) | (hn & ~gp0)) == 0 : ((hp & ~gp0) | (hn & ~gn0)) == 0;
+              for (int w = 1; w < W && ok; ++w) {
+                hp = hm[w];
+                hn = hm[W + w];
+                const uint64_t gpw = gm[w], gnw = gm[W + w];
+                ok = pol ? ((hp & ~gnw) | (hn & ~gpw)) == 0 : ((hp & ~gpw) | (hn & ~gnw)) == 0;
+              }
+              if (ok && magnitude_below(keys + (size_t)h * stride, g, n)) dead = true;
+            }
           }
         }
       }
+      if (valid) alive[p] = dead ? 0u : 1u;
     }
   }
-  alive[p] = dead ? 0u : 1u;
 }
 
 hipError_t launch_filter(hipStream_t s, graver_ctx* ctx, int n, const int8_t* in, int64_t count_in,
@@ -366,8 +405,11 @@ hipError_t launch_filter(hipStream_t s, graver_ctx* ctx, int n, const int8_t* in
   hipLaunchKernelGGL(k_codes, dim3(u256), dim3(256), 0, s, canon, stride, U, C, code, hist);
   scan_exclusive(s, hist, boff, ncode + 1, scr2);
   hipLaunchKernelGGL(k_bucket_scatter, dim3(u256), dim3(256), 0, s, code, U, boff, cur, bl);
-  hipLaunchKernelGGL(k_pairs_bucket, dim3(u256), dim3(256), 0, s, canon, stride, n, U, W, mskb, lo, boff, bl, C,
-                     alive);
+  const int tile_n = W <= 4 ? 256 : (W <= 16 ? 64 : 16);
+  const size_t jshm = (size_t)tile_n * (2 * W * sizeof(uint64_t) + sizeof(uint32_t));
+  const unsigned jgrid = ncode < 65535u ? ncode : 65535u;
+  hipLaunchKernelGGL(k_pairs_join, dim3(jgrid), dim3(kJoinThreads), jshm, s, canon, stride, n, W, mskb, lo, boff, bl,
+                     C, ncode, tile_n, alive);
   scan_exclusive(s, alive, pos, U, scr);
   hipMemcpyAsync(&hlast[0], pos + U - 1, 4, hipMemcpyDeviceToHost, s);
   hipMemcpyAsync(&hlast[1], alive + U - 1, 4, hipMemcpyDeviceToHost, s);

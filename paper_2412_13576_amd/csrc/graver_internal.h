@@ -32,7 +32,7 @@ enum Slot : int {
   WS_F_CANON, WS_F_UNIQ, WS_F_L1, WS_F_MASK, WS_F_LO, WS_F_ALIVE, WS_F_OUT,
   WS_A_R, WS_A_PART, WS_A_DONE, WS_A_QG, WS_A_TAB, WS_A_PX, WS_A_STEPS,
   WS_MF_B, WS_MF_BT, WS_MF_STATE, WS_MISC,
-  WS_F_CODE, WS_F_HIST, WS_F_OFF, WS_F_CUR, WS_F_BL, WS_A_QFLAG,
+  WS_F_CODE, WS_F_HIST, WS_F_OFF, WS_F_CUR, WS_F_BL, WS_A_QFLAG, WS_LOG, WS_LOG_COUNT,
 };
 void* ws_get(graver_ctx* ctx, int slot, size_t bytes, graver_status* st);
 
@@ -50,6 +50,15 @@ struct PoolDev {
 };
 inline int key_stride(int n) { return (n + 15) / 16 * 16; }
 
+// Append-only candidate log written by the MFMA descent (rows of `stride`
+// bytes; all-zero rows are unused slots) and later inserted into the pool.
+struct LogDev {
+  int8_t* rows;
+  uint32_t* count;  // rows reserved so far (may exceed cap)
+  uint32_t cap;
+  int32_t stride;
+};
+
 // Counters written by the descent kernels (atomic adds, int64).
 enum Counter : int { C_EMIT = 0, C_INBOX, C_RANGE, C_NCOUNTERS };
 
@@ -64,6 +73,8 @@ struct DescentArgs {
   const double* bc;     // 2*T bias corrections (device): [2k] = 1-b1^t, [2k+1] = 1-b2^t
   int32_t collect;
   int32_t bf16_iters;   // MFMA path: iterations k < bf16_iters use the bf16 hi/lo forward
+  int32_t lim_uniform;  // u_i - l_i when equal for every i, else -1
+  LogDev log;           // MFMA path: candidate log
 };
 
 hipError_t launch_init_box(hipStream_t s, int n, int d, int64_t N, const double* P,
@@ -84,6 +95,7 @@ hipError_t launch_f32_state_io(hipStream_t s, int n, int d, int64_t N, float* st
                                double* z, double* m, double* v, int to_device);
 
 hipError_t launch_pool_clear(hipStream_t s, PoolDev p);
+hipError_t launch_log_insert(hipStream_t s, LogDev log, PoolDev pool);
 hipError_t launch_verify(hipStream_t s, PoolDev p, uint32_t count, int m, const int64_t* A,
                          unsigned int* bad, int a_small);
 hipError_t launch_sort_keys(hipStream_t s, const int8_t* keys, int stride, int n, uint32_t count,

@@ -22,6 +22,28 @@ hipError_t launch_pool_clear(hipStream_t s, PoolDev p) {
   return hipGetLastError();
 }
 
+// Insert the rows of the candidate log into the pool, one thread per row;
+// all-zero rows are unused slots (a candidate is never zero).
+__global__ void k_log_insert(LogDev log, PoolDev pool) {
+  const uint32_t nrows = min(*log.count, log.cap);
+  const int nwords = log.stride / 8;
+  for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < nrows; r += gridDim.x * blockDim.x) {
+    const uint64_t* key = reinterpret_cast<const uint64_t*>(log.rows + (size_t)r * log.stride);
+    bool nz = false;
+    for (int w = 0; w < nwords; ++w) nz |= key[w] != 0;
+    if (!nz) continue;
+    pool_insert(pool, key, hash_key_words(key, nwords));
+  }
+}
+
+hipError_t launch_log_insert(hipStream_t s, LogDev log, PoolDev pool) {
+  unsigned blocks = (unsigned)((log.cap + 255) / 256);
+  if (blocks > 8192) blocks = 8192;
+  if (blocks == 0) blocks = 1;
+  hipLaunchKernelGGL(k_log_insert, dim3(blocks), dim3(256), 0, s, log, pool);
+  return hipGetLastError();
+}
+
 // One thread per key: every row of A must annihilate the key exactly
 // (condition C1).  A is staged in LDS as int32 when every |A_ij| < 2^23, so
 // each row sum is below 2^23 * 127 * n < 2^63 in int64 accumulation; the key

@@ -34,7 +34,12 @@ __device__ __forceinline__ uint64_t hash_final(uint64_t h) {
 // Hash of a key row held as 64-bit words (stride/8 words, zero padded).
 __device__ __forceinline__ uint64_t hash_key_words(const uint64_t* w, int nwords) {
   uint64_t h = 0x9E3779B97F4A7C15ull;
-  for (int i = 0; i < nwords; ++i) h = hash_mix(h, w[i]);
+  int i = 0;
+  for (; i + 4 <= nwords; i += 4) {  // four independent loads in flight
+    uint64_t a = w[i], b = w[i + 1], c = w[i + 2], d = w[i + 3];
+    h = hash_mix(hash_mix(hash_mix(hash_mix(h, a), b), c), d);
+  }
+  for (; i < nwords; ++i) h = hash_mix(h, w[i]);
   return hash_final(h);
 }
 
