@@ -344,13 +344,42 @@ graver_status graver_extract(graver_ctx* ctx, const graver_problem* prob,
       if (!lg.rows) return st;
       lg.count = (uint32_t*)ws_get(ctx, WS_LOG_COUNT, 64, &st);
       if (!lg.count) return st;
-      HIP_TRY(hipMemsetAsync(lg.count, 0, 64, s), "clear log count");
+      const size_t sbytes = f32_state_floats(n, d, N) * sizeof(float);
+      float* fbak = (float*)ws_get(ctx, WS_MF_BAK, sbytes, &st);
+      if (!fbak) return st;
+      unsigned long long* cbak = (unsigned long long*)ws_get(ctx, WS_MISC2, 64, &st);
+      if (!cbak) return st;
       da.log = lg;
-      EventTimer tm(s);
-      if (T > 0)
-        HIP_TRY(launch_descent_f32(s, da, Bp, BTp, fstate, pool, counters, zrange), "descent fp32");
-      stt.ms_descent = tm.stop_ms();
-      if (prm->collect && T > 0) HIP_TRY(launch_log_insert(s, lg, pool), "log insert");
+      const int bf16_total = da.bf16_iters;
+      // The candidate log holds pool_capacity rows per launch.  A launch whose
+      // log overflows is rolled back (state and counters) and replayed in two
+      // halves, so every candidate reaches the pool.
+      int done = 0, chunk = T;
+      while (done < T) {
+        const int c = std::min(chunk, T - done);
+        DescentArgs dc = da;
+        dc.T = c;
+        dc.bc = dbc + 2 * (size_t)done;
+        dc.bf16_iters = std::max(0, std::min(c, bf16_total - done));
+        HIP_TRY(hipMemcpyAsync(fbak, fstate, sbytes, hipMemcpyDeviceToDevice, s), "state backup");
+        HIP_TRY(hipMemcpyAsync(cbak, counters, 64, hipMemcpyDeviceToDevice, s), "counter backup");
+        HIP_TRY(hipMemsetAsync(lg.count, 0, 64, s), "clear log count");
+        EventTimer tm(s);
+        HIP_TRY(launch_descent_f32(s, dc, Bp, BTp, fstate, pool, counters, zrange), "descent fp32");
+        stt.ms_descent += tm.stop_ms();
+        uint32_t lflag[2] = {0, 0};
+        HIP_TRY(hipMemcpyAsync(lflag, lg.count, sizeof(lflag), hipMemcpyDeviceToHost, s), "log flag");
+        HIP_TRY(hipStreamSynchronize(s), "sync");
+        if (lflag[1]) {
+          if (c == 1) return set_error(GRAVER_E_POOL_FULL, "one iteration yields more candidates than pool_capacity");
+          HIP_TRY(hipMemcpyAsync(fstate, fbak, sbytes, hipMemcpyDeviceToDevice, s), "state rollback");
+          HIP_TRY(hipMemcpyAsync(counters, cbak, 64, hipMemcpyDeviceToDevice, s), "counter rollback");
+          chunk = std::max(1, c / 2);
+          continue;
+        }
+        if (prm->collect) HIP_TRY(launch_log_insert(s, lg, pool), "log insert");
+        done += c;
+      }
       HIP_TRY(launch_f32_state_io(s, n, d, N, fstate, z, mm, vv, 0), "state out");
     }
   }

@@ -215,7 +215,7 @@ __device__ __forceinline__ void zero_rows(const LogDev& log, uint32_t first, uin
 }
 
 template <int NB, int DB>
-__global__ __launch_bounds__(64 * kWavesPerBlock, 2) void k_descent_f32(DescentArgs a, const floatx4* __restrict__ FA,
+__global__ __launch_bounds__(64 * kWavesPerBlock, 1) void k_descent_f32(DescentArgs a, const floatx4* __restrict__ FA,
                                                                          const shortx4* __restrict__ FB,
                                                                          const shortx4* __restrict__ BT,
                                                                          float* __restrict__ state, PoolDev pool,
@@ -227,7 +227,6 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 2) void k_descent_f32(DescentA
   shortx4* sFB = reinterpret_cast<shortx4*>(sFA + NB * DB * 64);
   shortx4* sBT = sFB + NB * DB * 64;
   int* sLim = reinterpret_cast<int*>(sBT + NB * DB * 64);
-  int8_t* sKeys = reinterpret_cast<int8_t*>(sLim + 16 * NB);
   const int stride = pool.stride;
 
   for (int t = threadIdx.x; t < NB * DB * 64; t += blockDim.x) {
@@ -237,7 +236,6 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 2) void k_descent_f32(DescentA
   }
   for (int i = threadIdx.x; i < 16 * NB; i += blockDim.x)
     sLim[i] = i < a.n ? (int)(a.u[i] - a.l[i]) : 0;
-  for (int t = threadIdx.x; t < kWavesPerBlock * 16 * stride; t += blockDim.x) sKeys[t] = 0;
   __syncthreads();
 
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -245,7 +243,6 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 2) void k_descent_f32(DescentA
   const int64_t w = (int64_t)blockIdx.x * kWavesPerBlock + wid;
   const int64_t sidx = w * 16 + sl;
   const bool svalid = sidx < a.N;
-  int8_t* myKeys = sKeys + wid * 16 * stride;
 
   float z[DB][4], m[DB][4], v[DB][4], rp[DB][4];
   int gi[NB][4];
@@ -269,6 +266,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 2) void k_descent_f32(DescentA
   unsigned long long n_emit = 0, n_inbox = 0, n_range = 0;
   uint32_t lbase = 0, lused = 0;
   int lleft = 0;
+  bool log_full = false;
   const float lam1 = (float)a.lambda1, lam2 = (float)a.lambda2;
   const float b1 = (float)a.beta1, b2 = (float)a.beta2, omb1 = (float)a.one_minus_b1, omb2 = (float)a.one_minus_b2;
   const float eps = (float)a.eps;
@@ -308,6 +306,10 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 2) void k_descent_f32(DescentA
             acc[ib] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[ib][r], z[jb][r], acc[ib], 0, 0, 0);
       }
     }
+    // Scheduling barriers keep the phases (forward, backward, Adam,
+    // collection) from being interleaved, which bounds live ranges: the
+    // kernel then fits 2 waves per SIMD without spills.
+    __builtin_amdgcn_sched_barrier(0);
     // ---- backward G^T = B^T sign(Y)^T on exact bf16 operands ----
     floatx4 gacc[DB];
 #pragma unroll
@@ -321,6 +323,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 2) void k_descent_f32(DescentA
       for (int jb = 0; jb < DB; ++jb)
         gacc[jb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(sBT[(jb * NB + ib) * 64 + lane], sg, gacc[jb], 0, 0, 0);
     }
+    __builtin_amdgcn_sched_barrier(0);
     // ---- barrier term: ||z||_inf and ties, per start (4 lanes) ----
     float mu = 0.f;
 #pragma unroll
@@ -360,6 +363,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 2) void k_descent_f32(DescentA
         dr[jb][r] = rn - rp[jb][r];
         rp[jb][r] = rn;
       }
+    __builtin_amdgcn_sched_barrier(0);
     if (!a.collect) continue;
     // ---- per-start flags (the 4 lanes of a start agree afterwards) ----
     inrange = xand4(inrange);
@@ -408,6 +412,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 2) void k_descent_f32(DescentA
 #pragma unroll
         for (int r = 0; r < 4; ++r) gi[ib][r] += (int)dg[ib][r];
     }
+    __builtin_amdgcn_sched_barrier(0);
     if (__ballot(emit) == 0) continue;
     // ---- box test (condition C4) and nonzero test ----
     int inbox = 1, nonzero = 0;
@@ -433,14 +438,14 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 2) void k_descent_f32(DescentA
     // block.  Slots come from per-wave chunks of kLogChunk rows reserved with
     // one atomic; unused slots are zeroed (the log reader skips zero rows).
     const int npu = __popcll(pm);
-    if (npu > lleft) {
+    if (npu > lleft && !log_full) {
       if (lleft > 0) {
         zero_rows(log, lbase + lused, (uint32_t)lleft, lane);
         lleft = 0;
       }
       uint32_t nb = 0;
       if (lane == 0) nb = atomicAdd(log.count, (uint32_t)kLogChunk);
-      nb = __shfl(nb, 0, 64);
+      nb = __builtin_amdgcn_readfirstlane(nb);
       if (nb < log.cap) {
         const uint32_t end = min(log.cap, nb + (uint32_t)kLogChunk);
         lbase = nb;
@@ -448,7 +453,14 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 2) void k_descent_f32(DescentA
         lleft = (int)(end - nb);
       }
     }
-    if (npu <= lleft) {
+    if (npu > lleft) {
+      // the log is exhausted: flag it; the host replays this call in shorter
+      // pieces, so no candidate is lost
+      if (!log_full && lane == 0) atomicOr(log.count + 1, 1u);
+      log_full = true;
+      continue;
+    }
+    {
       const uint32_t rank = (uint32_t)__popcll(pm & ((1ull << sl) - 1ull));
       if (put) {
         uint32_t* row = reinterpret_cast<uint32_t*>(log.rows + (size_t)(lbase + lused + rank) * stride);
@@ -462,29 +474,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 2) void k_descent_f32(DescentA
       }
       lused += (uint32_t)npu;
       lleft -= npu;
-      continue;
     }
-    // ---- log exhausted: insert directly into the pool -------------------
-    if (put) {
-#pragma unroll
-      for (int ib = 0; ib < NB; ++ib)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int i = 16 * ib + 4 * q + r;
-          if (i < a.n) myKeys[sl * stride + i] = (int8_t)gi[ib][r];
-        }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (q == 0 && put) {
-      const uint64_t* key = reinterpret_cast<const uint64_t*>(myKeys + sl * stride);
-      uint64_t h = hash_key_words(key, stride / 8);
-      pool_insert(pool, key, h);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
   if (lleft > 0) zero_rows(log, lbase + lused, (uint32_t)lleft, lane);
 #pragma unroll
@@ -515,8 +505,7 @@ static hipError_t launch_nd(hipStream_t s, const DescentArgs& a, const float* FA
   const int lim_uniform = a.lim_uniform;
   const int64_t nw = n_waves(a.N);
   const int64_t per = nw * 4 * DB * 64;
-  const size_t shmem = (size_t)NB * DB * 64 * (sizeof(floatx4) + 2 * sizeof(shortx4)) + 16 * NB * sizeof(int) +
-                       (size_t)kWavesPerBlock * 16 * pool.stride;
+  const size_t shmem = (size_t)NB * DB * 64 * (sizeof(floatx4) + 2 * sizeof(shortx4)) + 16 * NB * sizeof(int);
   auto kern = k_descent_f32<NB, DB>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
   if (e != hipSuccess) return e;

@@ -12,7 +12,7 @@
 struct graver_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
-  static constexpr int kSlots = 48;
+  static constexpr int kSlots = 56;
   void* buf[kSlots] = {};
   size_t cap[kSlots] = {};
   void* host_pinned = nullptr;  // small pinned staging area
@@ -32,7 +32,7 @@ enum Slot : int {
   WS_F_CANON, WS_F_UNIQ, WS_F_L1, WS_F_MASK, WS_F_LO, WS_F_ALIVE, WS_F_OUT,
   WS_A_R, WS_A_PART, WS_A_DONE, WS_A_QG, WS_A_TAB, WS_A_PX, WS_A_STEPS,
   WS_MF_B, WS_MF_BT, WS_MF_STATE, WS_MISC,
-  WS_F_CODE, WS_F_HIST, WS_F_OFF, WS_F_CUR, WS_F_BL, WS_A_QFLAG, WS_LOG, WS_LOG_COUNT,
+  WS_F_CODE, WS_F_HIST, WS_F_OFF, WS_F_CUR, WS_F_BL, WS_A_QFLAG, WS_LOG, WS_LOG_COUNT, WS_MF_BAK, WS_MISC2,
 };
 void* ws_get(graver_ctx* ctx, int slot, size_t bytes, graver_status* st);
 
