@@ -29,6 +29,7 @@ SOURCES = {
     "pool.hip": [],
     "descent_fp64.hip": ["-ffp-contract=off"],
     "descent_f32.hip": ["-ffp-contract=fast"],
+    "descent_big.hip": ["-ffp-contract=fast"],
     "filter.hip": [],
     "augment.hip": ["-ffp-contract=off"],
 }

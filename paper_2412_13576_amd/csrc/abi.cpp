@@ -319,24 +319,46 @@ graver_status graver_extract(graver_ctx* ctx, const graver_problem* prob,
       if (T > 0) HIP_TRY(launch_descent_fp64(s, da, z, mm, vv, rp, sg, ks, pool, counters), "descent fp64");
       stt.ms_descent = tm.stop_ms();
     } else {
-      if (!descent_f32_supported(n, d))
-        return set_error(GRAVER_E_INVALID, "the MFMA descent supports n <= 128, d <= 128 in this build");
-      float* Bp = (float*)ws_get(ctx, WS_MF_B, f32_pack_floats(n, d) * sizeof(float), &st);
-      if (!Bp) return st;
-      float* BTp = (float*)ws_get(ctx, WS_MF_BT, f32_pack_floats(n, d) * sizeof(float), &st);
-      if (!BTp) return st;
+      const bool small = descent_f32_supported(n, d);
+      if (!small && !descent_big_supported(n, d))
+        return set_error(GRAVER_E_INVALID, "the MFMA descent supports n <= 1024 and d <= 512");
+      if (!small && da.bf16_iters > 0 && !descent_big_bf16_supported(d))
+        return set_error(GRAVER_E_INVALID, "the BF16 form supports d <= 384 for n > 128");
+      // |B_ij| <= 256 makes every bf16 operand exact; row l1 norms bound the
+      // exact range of the candidate map.
       int* rowl1 = (int*)ws_get(ctx, WS_MISC, 64, &st);
       if (!rowl1) return st;
-      float* fstate = (float*)ws_get(ctx, WS_MF_STATE, f32_state_floats(n, d, N) * sizeof(float), &st);
-      if (!fstate) return st;
-      HIP_TRY(launch_f32_pack(s, n, d, prob->B, Bp, BTp, rowl1), "pack basis");
+      float* Bp = nullptr;
+      float* BTp = nullptr;
+      unsigned char* img = nullptr;
+      if (small) {
+        Bp = (float*)ws_get(ctx, WS_MF_B, f32_pack_floats(n, d) * sizeof(float), &st);
+        if (!Bp) return st;
+        BTp = (float*)ws_get(ctx, WS_MF_BT, f32_pack_floats(n, d) * sizeof(float), &st);
+        if (!BTp) return st;
+        HIP_TRY(launch_f32_pack(s, n, d, prob->B, Bp, BTp, rowl1), "pack basis");
+      } else {
+        img = (unsigned char*)ws_get(ctx, WS_MF_B, big_image_bytes(n, d), &st);
+        if (!img) return st;
+        HIP_TRY(launch_big_pack(s, n, d, prob->B, img), "pack basis");
+        HIP_TRY(launch_rowl1(s, n, d, prob->B, rowl1), "row norms");
+      }
       int hrow[2] = {0, 0};
       HIP_TRY(hipMemcpyAsync(hrow, rowl1, 2 * sizeof(int), hipMemcpyDeviceToHost, s), "row l1");
       HIP_TRY(hipStreamSynchronize(s), "sync");
       if (hrow[1] > 256)
         return set_error(GRAVER_E_INVALID, "the MFMA descent needs |B_ij| <= 256 (exact bf16 operands)");
-      float zrange = (float)std::min(1073741824.0, std::floor(16777216.0 / std::max(hrow[0], 1)));
-      HIP_TRY(launch_f32_state_io(s, n, d, N, fstate, z, mm, vv, 1), "state in");
+      const float zrange = (float)std::min(1073741824.0, std::floor(16777216.0 / std::max(hrow[0], 1)));
+      const int DBlay = small ? (d + 15) / 16 : descent_big_dbp(d);
+      const size_t sfloats = small ? f32_state_floats(n, d, N) : big_state_floats(d, N);
+      float* fstate = (float*)ws_get(ctx, WS_MF_STATE, sfloats * sizeof(float), &st);
+      if (!fstate) return st;
+      int8_t* kscr = nullptr;
+      if (!small) {
+        kscr = (int8_t*)ws_get(ctx, WS_KEYSCRATCH, ((size_t)N + 64) * pool.stride, &st);
+        if (!kscr) return st;
+      }
+      HIP_TRY(launch_state_io_db(s, d, DBlay, N, fstate, z, mm, vv, 1), "state in");
       LogDev lg{};
       lg.stride = pool.stride;
       lg.cap = prm->collect ? pool.cap : 0u;
@@ -344,7 +366,7 @@ graver_status graver_extract(graver_ctx* ctx, const graver_problem* prob,
       if (!lg.rows) return st;
       lg.count = (uint32_t*)ws_get(ctx, WS_LOG_COUNT, 64, &st);
       if (!lg.count) return st;
-      const size_t sbytes = f32_state_floats(n, d, N) * sizeof(float);
+      const size_t sbytes = sfloats * sizeof(float);
       float* fbak = (float*)ws_get(ctx, WS_MF_BAK, sbytes, &st);
       if (!fbak) return st;
       unsigned long long* cbak = (unsigned long long*)ws_get(ctx, WS_MISC2, 64, &st);
@@ -356,7 +378,9 @@ graver_status graver_extract(graver_ctx* ctx, const graver_problem* prob,
       // halves, so every candidate reaches the pool.
       int done = 0, chunk = T;
       while (done < T) {
-        const int c = std::min(chunk, T - done);
+        int c = std::min(chunk, T - done);
+        // a launch of the large-basis kernel uses a single forward form
+        if (!small && done < bf16_total) c = std::min(c, bf16_total - done);
         DescentArgs dc = da;
         dc.T = c;
         dc.bc = dbc + 2 * (size_t)done;
@@ -365,7 +389,10 @@ graver_status graver_extract(graver_ctx* ctx, const graver_problem* prob,
         HIP_TRY(hipMemcpyAsync(cbak, counters, 64, hipMemcpyDeviceToDevice, s), "counter backup");
         HIP_TRY(hipMemsetAsync(lg.count, 0, 64, s), "clear log count");
         EventTimer tm(s);
-        HIP_TRY(launch_descent_f32(s, dc, Bp, BTp, fstate, pool, counters, zrange), "descent fp32");
+        if (small)
+          HIP_TRY(launch_descent_f32(s, dc, Bp, BTp, fstate, pool, counters, zrange), "descent mfma");
+        else
+          HIP_TRY(launch_descent_big(s, dc, img, fstate, kscr, counters), "descent mfma (large)");
         stt.ms_descent += tm.stop_ms();
         uint32_t lflag[2] = {0, 0};
         HIP_TRY(hipMemcpyAsync(lflag, lg.count, sizeof(lflag), hipMemcpyDeviceToHost, s), "log flag");
@@ -380,7 +407,8 @@ graver_status graver_extract(graver_ctx* ctx, const graver_problem* prob,
         if (prm->collect) HIP_TRY(launch_log_insert(s, lg, pool), "log insert");
         done += c;
       }
-      HIP_TRY(launch_f32_state_io(s, n, d, N, fstate, z, mm, vv, 0), "state out");
+      HIP_TRY(launch_state_io_db(s, d, DBlay, N, fstate, z, mm, vv, 0), "state out");
+
     }
   }
   HIP_TRY(hipGetLastError(), "descent launch");

@@ -1,0 +1,475 @@
+// Descent of eq. loss with Parallel Extraction (Algorithm 2) on gfx950 matrix
+// cores for large bases (n up to 1024, d up to 512).
+//
+// A wave owns 16 starts; a block is 4 waves (one per SIMD) that share the
+// basis, which is streamed through LDS one 16-row block at a time (double
+// buffered, the next block prefetched into registers while the current one
+// is used).  z and the gradient accumulators stay in registers; m and v are
+// read and written once per iteration in the wave-native layout.  Per row
+// block ib the wave computes
+//   y_ib   = B_ib z                      (binary32 MFMA, or bf16 hi/lo split)
+//   G     += B_ib^T sign(y_ib)           (exact bf16 operands, fp32 sums)
+//   g_ib   = B_ib r   for the previous iterate r = round(z)   (exact bf16)
+// so the exact candidate of iterate t is formed during iteration t+1 (and a
+// final pass forms the last one).  Rounded coordinates beyond |r| <= 256 are
+// not exact bf16 operands: such an iterate yields no candidate (counted as
+// out of range).  Candidate rows are staged per start in a global scratch
+// row, and rows that pass the box test are appended to the candidate log.
+#include <hip/hip_runtime.h>
+
+#include "graver_internal.h"
+
+namespace graver {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef short shortx4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int kWaves = 4;
+constexpr int kBigLogChunk = 64;
+
+inline int blk16(int x) { return (x + 15) / 16; }
+
+int big_db(int d) {
+  static const int sizes[] = {8, 12, 16, 20, 24, 28, 32};
+  int db = blk16(d);
+  for (int s : sizes)
+    if (db <= s) return s;
+  return -1;
+}
+
+inline int64_t big_waves(int64_t N) {
+  int64_t w = (N + 15) / 16;
+  return (w + kWaves - 1) / kWaves * kWaves;
+}
+
+__device__ __forceinline__ short bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f(short h) { return __uint_as_float((uint32_t)(uint16_t)h << 16); }
+__device__ __forceinline__ short sign_bf16(float y) {
+  return y > 0.f ? (short)0x3F80 : (y < 0.f ? (short)0xBF80 : (short)0);
+}
+__device__ __forceinline__ short int_bf16(float v) { return (short)(__float_as_uint(v) >> 16); }  // |v| <= 256, integer
+
+__device__ __forceinline__ float xmax4(float x) {
+  x = fmaxf(x, __shfl_xor(x, 16, 64));
+  return fmaxf(x, __shfl_xor(x, 32, 64));
+}
+__device__ __forceinline__ float xsum4(float x) {
+  x += __shfl_xor(x, 16, 64);
+  return x + __shfl_xor(x, 32, 64);
+}
+__device__ __forceinline__ int xor4(int x) {
+  x |= __shfl_xor(x, 16, 64);
+  return x | __shfl_xor(x, 32, 64);
+}
+__device__ __forceinline__ int xand4(int x) {
+  x &= __shfl_xor(x, 16, 64);
+  return x & __shfl_xor(x, 32, 64);
+}
+
+// Per row block ib (16 rows), for DBP column blocks:
+//   FA[jb*64 + l] float4 (B[16ib + l%16][16jb + 4(l/16) + r])
+//   FB[jb*64 + l] 4 x bf16, same entries
+//   BT[jb*64 + l] 4 x bf16 (B[16ib + 4(l/16) + r][16jb + l%16])
+// laid out as [FA | FB | BT], chunk_bytes = DBP * 64 * 32 bytes.
+__global__ void k_pack_big(int n, int d, int NB, int DBP, const int64_t* B, unsigned char* img) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  int per = DBP * 64;
+  if (t >= NB * per) return;
+  int ib = t / per, rest = t % per, jb = rest / 64, l = rest % 64;
+  unsigned char* chunk = img + (size_t)ib * per * 32;
+  float* FA = reinterpret_cast<float*>(chunk);
+  short* FB = reinterpret_cast<short*>(chunk + (size_t)per * 16);
+  short* BT = reinterpret_cast<short*>(chunk + (size_t)per * 24);
+  int i = 16 * ib + l % 16;
+  for (int r = 0; r < 4; ++r) {
+    int j = 16 * jb + 4 * (l / 16) + r;
+    int64_t b = (i < n && j < d) ? B[(size_t)i * d + j] : 0;
+    FA[(size_t)rest * 4 + r] = (float)b;
+    FB[(size_t)rest * 4 + r] = (short)(__float_as_uint((float)b) >> 16);
+  }
+  int j2 = 16 * jb + l % 16;
+  for (int r = 0; r < 4; ++r) {
+    int i2 = 16 * ib + 4 * (l / 16) + r;
+    int64_t b = (i2 < n && j2 < d) ? B[(size_t)i2 * d + j2] : 0;
+    BT[(size_t)rest * 4 + r] = (short)(__float_as_uint((float)b) >> 16);
+  }
+}
+
+struct BigArgs {
+  DescentArgs a;
+  int NB;
+  const unsigned char* img;
+  float* z;  // wave-native state (z, then m, then v, each `per` floats)
+  int64_t per;
+  int8_t* scratch;  // one key row per start
+  int stride;
+};
+
+__device__ __forceinline__ void zero_rows_big(const LogDev& log, uint32_t first, uint32_t rows, int lane) {
+  const int dw = log.stride / 4;
+  uint32_t* base = reinterpret_cast<uint32_t*>(log.rows + (size_t)first * log.stride);
+  for (uint32_t t = lane; t < rows * (uint32_t)dw; t += 64) base[t] = 0u;
+}
+
+template <int DBP, bool BF16F>
+__global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(BigArgs g, unsigned long long* counters) {
+  const DescentArgs& a = g.a;
+  constexpr int kChunkBytes = DBP * 64 * 32;
+  constexpr int kChunkU4 = kChunkBytes / 16;               // uint4 per chunk
+  constexpr int kPerThread = kChunkU4 / (64 * kWaves);     // DBP * 2
+  extern __shared__ __align__(16) unsigned char smem[];
+  uint4* buf0 = reinterpret_cast<uint4*>(smem);
+  uint4* buf1 = buf0 + kChunkU4;
+  int* sLim = reinterpret_cast<int*>(buf1 + kChunkU4);
+
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int q = lane >> 4, sl = lane & 15;
+  const int64_t w = (int64_t)blockIdx.x * kWaves + wid;
+  const int64_t sidx = w * 16 + sl;
+  const bool svalid = sidx < a.N;
+  const int NB = g.NB;
+  const int stride = g.stride;
+  for (int i = threadIdx.x; i < 16 * NB; i += blockDim.x) sLim[i] = i < a.n ? (int)(a.u[i] - a.l[i]) : 0;
+
+  float z[DBP][4];
+  // per-wave base pointers (uniform) with 32-bit lane offsets
+  const size_t wbase = (size_t)w * 4 * DBP * 64;
+  float* Z = g.z + wbase;
+  float* M = g.z + g.per + wbase;
+  float* V = g.z + 2 * g.per + wbase;
+  const int base = lane;
+#pragma unroll
+  for (int jb = 0; jb < DBP; ++jb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) z[jb][r] = Z[base + (4 * jb + r) * 64];
+
+  const float lam1 = (float)a.lambda1, lam2 = (float)a.lambda2;
+  const float b1 = (float)a.beta1, b2 = (float)a.beta2, omb1 = (float)a.one_minus_b1, omb2 = (float)a.one_minus_b2;
+  const float eps = (float)a.eps;
+  const uint4* img = reinterpret_cast<const uint4*>(g.img);
+  uint32_t* srow = reinterpret_cast<uint32_t*>(g.scratch + (size_t)sidx * stride);
+
+  int changed = 0;       // the current iterate's rounding differs from the previous one
+  bool alive = svalid;   // start still inside the exact range
+  unsigned long long n_emit = 0, n_inbox = 0, n_range = 0;
+  uint32_t lbase = 0, lused = 0;
+  int lleft = 0;
+  bool log_full = false;
+  const LogDev& log = a.log;
+
+  for (int k = 0; k <= a.T; ++k) {
+    const bool descend = k < a.T;
+    const bool needg = a.collect && k > 0 && __ballot(changed && alive) != 0;
+    if (!descend && !needg) break;
+    const bool bf16f = BF16F && descend;
+    // rounded coordinates of the current iterate as exact bf16 operands
+    shortx4 rp[DBP];
+    int inrange = 1;
+    if (needg) {
+#pragma unroll
+      for (int jb = 0; jb < DBP; ++jb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float rv = rintf(z[jb][r]);
+          inrange &= fabsf(rv) <= 256.f;
+          rp[jb][r] = int_bf16(rv);
+        }
+      inrange = xand4(inrange);
+    }
+    shortx4 hi[BF16F ? DBP : 1], lo[BF16F ? DBP : 1];
+    if constexpr (BF16F) {
+#pragma unroll
+      for (int jb = 0; jb < DBP; ++jb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          short h = bf16_rne(z[jb][r]);
+          hi[jb][r] = h;
+          lo[jb][r] = bf16_rne(z[jb][r] - bf16_to_f(h));
+        }
+    }
+    floatx4 G[DBP];
+#pragma unroll
+    for (int jb = 0; jb < DBP; ++jb) G[jb] = floatx4{0.f, 0.f, 0.f, 0.f};
+    int inbox = 1, nonzero = 0;
+
+    // stage row block 0
+    __syncthreads();
+    for (int t = 0; t < kPerThread; ++t) buf0[threadIdx.x + t * 64 * kWaves] = img[threadIdx.x + t * 64 * kWaves];
+    __syncthreads();
+    for (int ib = 0; ib < NB; ++ib) {
+      uint4* cur = (ib & 1) ? buf1 : buf0;
+      uint4* nxt = (ib & 1) ? buf0 : buf1;
+      uint4 pre[kPerThread];
+      const bool more = ib + 1 < NB;
+      if (more) {
+        const uint4* src = img + (size_t)(ib + 1) * kChunkU4;
+#pragma unroll
+        for (int t = 0; t < kPerThread; ++t) pre[t] = src[threadIdx.x + t * 64 * kWaves];
+      }
+      const floatx4* FA = reinterpret_cast<const floatx4*>(cur);
+      const shortx4* FB = reinterpret_cast<const shortx4*>(reinterpret_cast<unsigned char*>(cur) + DBP * 64 * 16);
+      const shortx4* BT = reinterpret_cast<const shortx4*>(reinterpret_cast<unsigned char*>(cur) + DBP * 64 * 24);
+      if (descend) {
+        floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
+        // column blocks in groups of 4 with scheduling barriers in between:
+        // bounds the number of LDS operands loaded ahead (register pressure)
+        if constexpr (BF16F) {
+#pragma unroll
+          for (int jg = 0; jg < DBP; jg += 4) {
+#pragma unroll
+            for (int jb = jg; jb < jg + 4; ++jb) {
+              const shortx4 A = FB[jb * 64 + lane];
+              acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, hi[jb], acc, 0, 0, 0);
+              acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, lo[jb], acc, 0, 0, 0);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+          }
+        } else {
+#pragma unroll
+          for (int jg = 0; jg < DBP; jg += 4) {
+#pragma unroll
+            for (int jb = jg; jb < jg + 4; ++jb) {
+              const floatx4 A = FA[jb * 64 + lane];
+#pragma unroll
+              for (int r = 0; r < 4; ++r) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A[r], z[jb][r], acc, 0, 0, 0);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+          }
+        }
+        shortx4 sg;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sg[r] = sign_bf16(acc[r]);
+#pragma unroll
+        for (int jg = 0; jg < DBP; jg += 4) {
+#pragma unroll
+          for (int jb = jg; jb < jg + 4; ++jb)
+            G[jb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(BT[jb * 64 + lane], sg, G[jb], 0, 0, 0);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+      if (needg) {
+        floatx4 gx = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int jg = 0; jg < DBP; jg += 4) {
+#pragma unroll
+          for (int jb = jg; jb < jg + 4; ++jb)
+            gx = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(FB[jb * 64 + lane], rp[jb], gx, 0, 0, 0);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        uint32_t wd = 0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int gv = (int)gx[r];
+          const int lim = a.lim_uniform >= 0 ? a.lim_uniform : sLim[16 * ib + 4 * q + r];
+          inbox &= (gv <= lim) & (gv >= -lim);
+          nonzero |= gv != 0;
+          wd |= ((uint32_t)(uint8_t)(int8_t)gv) << (8 * r);
+        }
+        if (svalid) srow[4 * ib + q] = wd;
+      }
+      __syncthreads();
+      if (more) {
+#pragma unroll
+        for (int t = 0; t < kPerThread; ++t) nxt[threadIdx.x + t * 64 * kWaves] = pre[t];
+      }
+      __syncthreads();
+    }
+
+    __builtin_amdgcn_sched_barrier(0);
+    if (needg) {
+      inbox = xand4(inbox);
+      nonzero = xor4(nonzero);
+      const bool em = changed && alive;
+      if (em && !inrange) alive = false;
+      const bool emit = em && inrange;
+      const bool put = emit && inbox && nonzero;
+      n_emit += (q == 0 && emit) ? 1 : 0;
+      n_inbox += (q == 0 && put) ? 1 : 0;
+      const uint64_t pm = __ballot(put && q == 0);
+      if (pm != 0) {
+        const int npu = __popcll(pm);
+        if (npu > lleft && !log_full) {
+          if (lleft > 0) {
+            zero_rows_big(log, lbase + lused, (uint32_t)lleft, lane);
+            lleft = 0;
+          }
+          uint32_t nb = 0;
+          if (lane == 0) nb = atomicAdd(log.count, (uint32_t)kBigLogChunk);
+          nb = __builtin_amdgcn_readfirstlane(nb);
+          if (nb < log.cap) {
+            const uint32_t end = min(log.cap, nb + (uint32_t)kBigLogChunk);
+            lbase = nb;
+            lused = 0;
+            lleft = (int)(end - nb);
+          }
+        }
+        if (npu > lleft) {
+          if (!log_full && lane == 0) atomicOr(log.count + 1, 1u);
+          log_full = true;
+        } else {
+          const uint32_t rank = (uint32_t)__popcll(pm & ((1ull << sl) - 1ull));
+          if (put) {
+            uint32_t* row = reinterpret_cast<uint32_t*>(log.rows + (size_t)(lbase + lused + rank) * stride);
+            for (int ib = 0; ib < NB; ++ib) row[4 * ib + q] = srow[4 * ib + q];
+          }
+          lused += (uint32_t)npu;
+          lleft -= npu;
+        }
+      }
+    }
+    if (!alive && svalid && q == 0 && descend && k > 0) ++n_range;
+    if (!descend) break;
+
+    __builtin_amdgcn_sched_barrier(0);
+    // barrier term, Adam, and the change flag of the new iterate
+    float mu = 0.f;
+#pragma unroll
+    for (int jb = 0; jb < DBP; ++jb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) mu = fmaxf(mu, fabsf(z[jb][r]));
+    mu = xmax4(mu);
+    float cnt = 0.f;
+#pragma unroll
+    for (int jb = 0; jb < DBP; ++jb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) cnt += fabsf(z[jb][r]) == mu ? 1.f : 0.f;
+    cnt = xsum4(cnt);
+    const bool bar = mu > 0.f && mu < 1.f;
+    const float wbar = bar ? lam2 / ((mu * mu) * cnt) : 0.f;
+    const double bc1 = a.bc[2 * k], bc2 = a.bc[2 * k + 1];
+    const float step = (float)(a.lr / bc1), ib2 = (float)(1.0 / bc2);
+    int ch = 0;
+    // m and v stream through registers in groups of 4 column blocks; the
+    // next group's loads are issued before the current group is computed
+    // (two register stages), and scheduling barriers keep the compiler from
+    // hoisting every load of the iteration at once.
+    constexpr int NG = DBP / 4;
+    float mv[2][4][4][2];
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int e = base + (4 * jb + r) * 64;
+        mv[0][jb][r][0] = M[e];
+        mv[0][jb][r][1] = V[e];
+      }
+#pragma unroll
+    for (int gi = 0; gi < NG; ++gi) {
+      const int cur = gi & 1, nx = cur ^ 1;
+      if (gi + 1 < NG) {
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int e = base + (4 * (4 * (gi + 1) + jj) + r) * 64;
+            mv[nx][jj][r][0] = M[e];
+            mv[nx][jj][r][1] = V[e];
+          }
+      }
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int jb = 4 * gi + jj;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float zj = z[jb][r];
+          float gg = G[jb][r] + lam1 * ((ceilf(zj) + floorf(zj)) - 2.f * zj);
+          if (bar && fabsf(zj) == mu) gg -= zj > 0.f ? wbar : -wbar;
+          const float mj = b1 * mv[cur][jj][r][0] + omb1 * gg;
+          const float vj = b2 * mv[cur][jj][r][1] + omb2 * (gg * gg);
+          const float zn = zj - (step * mj) * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(vj * ib2) + eps);
+          ch |= (rintf(zn) != rintf(zj)) | (k == 0);
+          z[jb][r] = zn;
+          const int e = base + (4 * jb + r) * 64;
+          M[e] = mj;
+          V[e] = vj;
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    changed = xor4(ch);
+  }
+#pragma unroll
+  for (int jb = 0; jb < DBP; ++jb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Z[base + (4 * jb + r) * 64] = z[jb][r];
+  if (lleft > 0) zero_rows_big(log, lbase + lused, (uint32_t)lleft, lane);
+  for (int o = 32; o > 0; o >>= 1) {
+    n_emit += __shfl_xor(n_emit, o, 64);
+    n_inbox += __shfl_xor(n_inbox, o, 64);
+    n_range += __shfl_xor(n_range, o, 64);
+  }
+  if (lane == 0) {
+    if (n_emit) atomicAdd(&counters[C_EMIT], n_emit);
+    if (n_inbox) atomicAdd(&counters[C_INBOX], n_inbox);
+    if (n_range) atomicAdd(&counters[C_RANGE], n_range);
+  }
+}
+
+template <int DBP, bool BF16F>
+hipError_t launch_big_t(hipStream_t s, const BigArgs& g, unsigned long long* counters) {
+  const int64_t nw = big_waves(g.a.N);
+  const size_t shmem = (size_t)2 * DBP * 64 * 32 + (size_t)16 * g.NB * sizeof(int);
+  auto kern = k_descent_big<DBP, BF16F>;
+  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3((unsigned)(nw / kWaves)), dim3(64 * kWaves), shmem, s, g, counters);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+bool descent_big_supported(int n, int d) { return n <= 1024 && d <= n && big_db(d) > 0; }
+bool descent_big_bf16_supported(int d) { return big_db(d) > 0 && big_db(d) <= 24; }
+int descent_big_dbp(int d) { return big_db(d); }
+size_t big_image_bytes(int n, int d) { return (size_t)blk16(n) * big_db(d) * 64 * 32; }
+size_t big_state_floats(int d, int64_t N) { return 3 * (size_t)big_waves(N) * 4 * big_db(d) * 64; }
+
+hipError_t launch_big_pack(hipStream_t s, int n, int d, const int64_t* B, unsigned char* img) {
+  int NB = blk16(n), DBP = big_db(d);
+  int total = NB * DBP * 64;
+  hipLaunchKernelGGL(k_pack_big, dim3((total + 255) / 256), dim3(256), 0, s, n, d, NB, DBP, B, img);
+  return hipGetLastError();
+}
+
+hipError_t launch_descent_big(hipStream_t s, const DescentArgs& a, const unsigned char* img, float* state,
+                              int8_t* scratch, unsigned long long* counters) {
+  BigArgs g{};
+  g.a = a;
+  g.NB = blk16(a.n);
+  g.img = img;
+  g.z = state;
+  const int DBP = big_db(a.d);
+  g.per = big_waves(a.N) * 4 * DBP * 64;
+  g.scratch = scratch;
+  g.stride = key_stride(a.n);
+  // the whole launch uses one forward form: bf16 when a.bf16_iters covers it
+  const bool bf = a.bf16_iters >= a.T && a.T > 0;
+  if (bf) {
+    switch (DBP) {
+      case 8: return launch_big_t<8, true>(s, g, counters);
+      case 12: return launch_big_t<12, true>(s, g, counters);
+      case 16: return launch_big_t<16, true>(s, g, counters);
+      case 20: return launch_big_t<20, true>(s, g, counters);
+      case 24: return launch_big_t<24, true>(s, g, counters);
+    }
+    return hipErrorInvalidValue;
+  }
+  switch (DBP) {
+    case 8: return launch_big_t<8, false>(s, g, counters);
+    case 12: return launch_big_t<12, false>(s, g, counters);
+    case 16: return launch_big_t<16, false>(s, g, counters);
+    case 20: return launch_big_t<20, false>(s, g, counters);
+    case 24: return launch_big_t<24, false>(s, g, counters);
+    case 28: return launch_big_t<28, false>(s, g, counters);
+    case 32: return launch_big_t<32, false>(s, g, counters);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace graver

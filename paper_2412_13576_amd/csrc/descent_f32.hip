@@ -127,6 +127,11 @@ __global__ void k_rowl1(int n, int d, const int64_t* B, int* out) {
   }
 }
 
+hipError_t launch_rowl1(hipStream_t s, int n, int d, const int64_t* B, int* rowl1) {
+  hipLaunchKernelGGL(k_rowl1, dim3(1), dim3(256), 0, s, n, d, B, rowl1);
+  return hipGetLastError();
+}
+
 hipError_t launch_f32_pack(hipStream_t s, int n, int d, const int64_t* B, float* Bp, float* BTp, int* rowl1) {
   int NB = blk(n), DB = blk(d);
   int total = NB * DB * 64;
@@ -167,8 +172,11 @@ __global__ void k_state_io(int d, int DB, int64_t N, int64_t nw, float* state, d
 
 hipError_t launch_f32_state_io(hipStream_t s, int n, int d, int64_t N, float* state, double* z, double* m,
                                double* v, int to_device) {
-  (void)n;
-  int DB = blk(d);
+  return launch_state_io_db(s, d, blk(d), N, state, z, m, v, to_device);
+}
+
+hipError_t launch_state_io_db(hipStream_t s, int d, int DB, int64_t N, float* state, double* z, double* m,
+                              double* v, int to_device) {
   int64_t nw = n_waves(N);
   int64_t per = nw * 4 * DB * 64;
   hipLaunchKernelGGL(k_state_io, dim3((unsigned)((per + 255) / 256)), dim3(256), 0, s, d, DB, N, nw, state, z,
@@ -355,7 +363,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 1) void k_descent_f32(DescentA
         const float vj = b2 * v[jb][r] + omb2 * (g * g);
         m[jb][r] = mj;
         v[jb][r] = vj;
-        const float zn = zj - __fdividef(step * mj, __fsqrt_rn(vj * ib2) + eps);
+        const float zn = zj - (step * mj) * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(vj * ib2) + eps);
         z[jb][r] = zn;
         const float rn = rintf(zn);
         changed |= (rn != rp[jb][r]) | (k == 0);

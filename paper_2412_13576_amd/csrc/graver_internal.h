@@ -94,6 +94,18 @@ size_t f32_state_floats(int n, int d, int64_t N);
 hipError_t launch_f32_state_io(hipStream_t s, int n, int d, int64_t N, float* state,
                                double* z, double* m, double* v, int to_device);
 
+hipError_t launch_state_io_db(hipStream_t s, int d, int DB, int64_t N, float* state, double* z, double* m,
+                              double* v, int to_device);
+bool descent_big_supported(int n, int d);
+bool descent_big_bf16_supported(int d);
+hipError_t launch_rowl1(hipStream_t s, int n, int d, const int64_t* B, int* rowl1);
+int descent_big_dbp(int d);
+size_t big_image_bytes(int n, int d);
+size_t big_state_floats(int d, int64_t N);
+hipError_t launch_big_pack(hipStream_t s, int n, int d, const int64_t* B, unsigned char* img);
+hipError_t launch_descent_big(hipStream_t s, const DescentArgs& a, const unsigned char* img, float* state,
+                              int8_t* scratch, unsigned long long* counters);
+
 hipError_t launch_pool_clear(hipStream_t s, PoolDev p);
 hipError_t launch_log_insert(hipStream_t s, LogDev log, PoolDev pool);
 hipError_t launch_verify(hipStream_t s, PoolDev p, uint32_t count, int m, const int64_t* A,

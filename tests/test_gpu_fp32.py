@@ -338,3 +338,24 @@ def test_precision_forms_recall(G, ctx, qp):
         rec[name] = len(C & R) / len(R)
     _say("precision recall", rec, "descent ms", times)
     assert rec["bf16"] >= rec["fp32"] - 0.05
+
+
+def test_log_overflow_replay_keeps_every_candidate(G, ctx):
+    """A pool_capacity smaller than the number of in-box events of one launch
+    (but not than the distinct set) makes the candidate log overflow; the
+    launch is rolled back and replayed in pieces, and the result equals the
+    large-capacity run."""
+    inst = W.tiny_instance(1004)
+    B = lattice.kernel_basis(inst.A)
+    N = 1000
+    _say("log overflow replay")
+    z0 = W.gaussian_starts(N, B.shape[1], 2.0, 56)
+    prob = G.DeviceProblem.from_numpy(inst.A, inst.b, inst.l, inst.u, B)
+    big = G.extract_params(N, 400, precision=G.GRAVER_FP32, init_mode=1, pool_capacity=1 << 20)
+    kb, sb = G.extract(ctx, prob, big, state={"z": _dev(z0)})
+    cap = int(kb.shape[0] * 1.05)
+    assert sb["inbox_events"] > cap  # one launch's log cannot hold every event
+    small = G.extract_params(N, 400, precision=G.GRAVER_FP32, init_mode=1, pool_capacity=cap)
+    ks, ss = G.extract(ctx, prob, small, state={"z": _dev(z0)})
+    _say("log overflow replay", "unique", kb.shape[0], "events", sb["inbox_events"], "cap", cap)
+    assert torch.equal(kb, ks)
