@@ -60,6 +60,8 @@ def main():
     ap.add_argument("--precision", choices=["fp32", "bf16"], default="fp32")
     ap.add_argument("--polish", type=int, default=200, help="bf16: final iterations in binary32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one 1 GiB device copy (a kernel of known traffic, for counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the hot path is measured on one MI355X "
@@ -92,6 +94,12 @@ def main():
         x, f, steps, best = G.augment(ctx, prob, obj, F, starts)
         return keys.shape[0], F.shape[0], st, f, steps, best
 
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for w in range(args.warmup):
         step(1000 + w)
     torch.cuda.synchronize()

@@ -116,6 +116,18 @@ typedef struct {
   int64_t max_steps; /* cap on moves per start (>= 0)                        */
 } graver_augment_params;
 
+/* Parameters of the initial-solution search (Section 3.3, eq. init_sol). */
+typedef struct {
+  int64_t n_starts; /* S, number of parallel starting points                 */
+  int32_t iters;    /* Adam steps per start                                  */
+  int32_t init_mode; /* 0: x ~ Uniform(l, u) by Philox4x32-10 from seed;
+                        1: starting points supplied in x0                    */
+  double lr, beta1, beta2, eps; /* Adam                                      */
+  double lambda3;   /* weight of the integrality term (paper: 0.1)           */
+  uint64_t seed;    /* Philox key for init_mode 0                            */
+  int64_t first_start; /* Philox counter offset of start 0 (init_mode 0)     */
+} graver_init_params;
+
 /* ---- context ---------------------------------------------------------- */
 
 /* Create a context on HIP device `device`.  The context owns device
@@ -197,6 +209,27 @@ graver_status graver_augment(graver_ctx* ctx, const graver_problem* prob,
                              int32_t S, const int64_t* x_starts,
                              const graver_augment_params* params, int64_t* x_out,
                              double* f_out, int64_t* steps_out, int32_t* best_out);
+
+/* Initial feasible solutions (Section 3.3, eq. init_sol).  From each of S
+ * starting points, `iters` Adam steps minimise
+ *     ||A x - b||^2 + lambda3 * sum_i (x_i - floor x_i)(ceil x_i - x_i)
+ * with x projected onto [l, u] after every step; then r = round-half-even(x)
+ * is feasible when A r = b exactly and l <= r <= u.  Arithmetic is binary64
+ * with a fixed order (residual res_i = (sum_j A_ij x_j) - b_i, gradient
+ * 2 sum_i A_ij res_i + lambda3 ((ceil x_j + floor x_j) - 2 x_j), ascending
+ * sums from 0, no fused multiply-add), so results are bit-reproducible.
+ * prob->B and prob->P are not used.  Inputs: x0 (device, S x n binary64,
+ * read when init_mode is 1, else may be NULL).  Outputs (device): x_out
+ * (S x n binary64, the final iterates, may be NULL), sol_out (S x n int64,
+ * the rounded points), feasible_out (S int32, 1 when feasible);
+ * *n_feasible (host, may be NULL) = number of feasible rows.  Errors:
+ * GRAVER_E_OVERFLOW when sum_j |A_ij| max(|l_j|, |u_j|) or |b_i| reaches
+ * 2^53 (the exact test then could not be done in int64 / the residual would
+ * not be exact). */
+graver_status graver_init_solutions(graver_ctx* ctx, const graver_problem* prob,
+                                    const graver_init_params* params, const double* x0,
+                                    double* x_out, int64_t* sol_out, int32_t* feasible_out,
+                                    int64_t* n_feasible);
 
 #ifdef __cplusplus
 }

@@ -321,9 +321,7 @@ graver_status graver_extract(graver_ctx* ctx, const graver_problem* prob,
     } else {
       const bool small = descent_f32_supported(n, d);
       if (!small && !descent_big_supported(n, d))
-        return set_error(GRAVER_E_INVALID, "the MFMA descent supports n <= 1024 and d <= 512");
-      if (!small && da.bf16_iters > 0 && !descent_big_bf16_supported(d))
-        return set_error(GRAVER_E_INVALID, "the BF16 form supports d <= 384 for n > 128");
+        return set_error(GRAVER_E_INVALID, "the MFMA descent supports n <= 1024 and d <= 256 in this build");
       // |B_ij| <= 256 makes every bf16 operand exact; row l1 norms bound the
       // exact range of the candidate map.
       int* rowl1 = (int*)ws_get(ctx, WS_MISC, 64, &st);
@@ -531,6 +529,100 @@ graver_status graver_augment(graver_ctx* ctx, const graver_problem* prob, const 
     return set_error(GRAVER_E_INVALID, "unknown objective kind");
   }
   return run_augment(ctx, a, x_starts, x_out, f_out, steps_out, best_out);
+}
+
+graver_status graver_init_solutions(graver_ctx* ctx, const graver_problem* prob,
+                                    const graver_init_params* prm, const double* x0,
+                                    double* x_out, int64_t* sol_out, int32_t* feasible_out,
+                                    int64_t* n_feasible) {
+  if (!ctx || !prm || !sol_out || !feasible_out) return set_error(GRAVER_E_INVALID, "NULL argument");
+  hipSetDevice(ctx->device);
+  if (!prob) return set_error(GRAVER_E_INVALID, "problem is NULL");
+  if (prob->m < 1 || prob->n < 1 || prob->n > 4096)
+    return set_error(GRAVER_E_INVALID, "need m >= 1 and 1 <= n <= 4096");
+  if (!prob->A || !prob->b || !prob->l || !prob->u)
+    return set_error(GRAVER_E_INVALID, "A, b, l, u must be device pointers");
+  const int m = prob->m, n = prob->n;
+  const int64_t S = prm->n_starts;
+  if (S < 1 || S > (int64_t)1 << 26 || prm->iters < 0)
+    return set_error(GRAVER_E_INVALID, "bad n_starts / iters");
+  if (prm->init_mode != 0 && prm->init_mode != 1) return set_error(GRAVER_E_INVALID, "bad init_mode");
+  if (prm->init_mode == 1 && !x0) return set_error(GRAVER_E_INVALID, "init_mode 1 needs x0");
+  if (!(prm->beta1 >= 0 && prm->beta1 < 1) || !(prm->beta2 >= 0 && prm->beta2 < 1))
+    return set_error(GRAVER_E_INVALID, "bad Adam parameters");
+  graver_status st = GRAVER_OK;
+  std::vector<int64_t> hA, hb, hl, hu;
+  if ((st = copy_to_host(ctx, hA, prob->A, (size_t)m * n)) != GRAVER_OK) return st;
+  if ((st = copy_to_host(ctx, hb, prob->b, (size_t)m)) != GRAVER_OK) return st;
+  if ((st = copy_to_host(ctx, hl, prob->l, (size_t)n)) != GRAVER_OK) return st;
+  if ((st = copy_to_host(ctx, hu, prob->u, (size_t)n)) != GRAVER_OK) return st;
+  const double lim = 9007199254740992.0;  // 2^53
+  for (int j = 0; j < n; ++j) {
+    if (hl[j] > hu[j]) return set_error(GRAVER_E_INVALID, "l <= u violated");
+    if (std::fabs((double)hl[j]) >= lim || std::fabs((double)hu[j]) >= lim)
+      return set_error(GRAVER_E_OVERFLOW, "bounds reach 2^53");
+  }
+  for (int i = 0; i < m; ++i) {
+    double row = 0.0;
+    for (int j = 0; j < n; ++j)
+      row += std::fabs((double)hA[(size_t)i * n + j]) *
+             std::max(std::fabs((double)hl[j]), std::fabs((double)hu[j]));
+    if (row >= lim || std::fabs((double)hb[i]) >= lim)
+      return set_error(GRAVER_E_OVERFLOW, "sum_j |A_ij| max(|l_j|, |u_j|) or |b_i| reaches 2^53");
+  }
+
+  hipStream_t s = ctx->stream;
+  const int T = prm->iters;
+  std::vector<double> hbc(2 * (size_t)std::max(T, 1));
+  for (int k = 0; k < T; ++k) {
+    double t = (double)k + 1;
+    hbc[2 * k] = 1.0 - std::pow(prm->beta1, t);
+    hbc[2 * k + 1] = 1.0 - std::pow(prm->beta2, t);
+  }
+  double* dbc = (double*)ws_get(ctx, WS_BC, hbc.size() * sizeof(double), &st);
+  if (!dbc) return st;
+  HIP_TRY(hipMemcpyAsync(dbc, hbc.data(), hbc.size() * sizeof(double), hipMemcpyHostToDevice, s),
+          "copy bias corrections");
+  const size_t sn = (size_t)S * n;
+  double* X = (double*)ws_get(ctx, WS_I_X, sn * sizeof(double), &st);
+  if (!X) return st;
+  double* M = (double*)ws_get(ctx, WS_I_M, sn * sizeof(double), &st);
+  if (!M) return st;
+  double* V = (double*)ws_get(ctx, WS_I_V, sn * sizeof(double), &st);
+  if (!V) return st;
+  double* R = (double*)ws_get(ctx, WS_I_R, (size_t)S * m * sizeof(double), &st);
+  if (!R) return st;
+  double* G = prm->init_mode == 0 ? (double*)ws_get(ctx, WS_I_G, sn * sizeof(double), &st) : nullptr;
+  if (prm->init_mode == 0 && !G) return st;
+  auto* cnt = (unsigned int*)ws_get(ctx, WS_FLAGS, 64, &st);
+  if (!cnt) return st;
+
+  InitArgs a{};
+  a.m = m;
+  a.n = n;
+  a.T = T;
+  a.S = S;
+  a.A = prob->A;
+  a.b = prob->b;
+  a.l = prob->l;
+  a.u = prob->u;
+  a.lr = prm->lr;
+  a.beta1 = prm->beta1;
+  a.beta2 = prm->beta2;
+  a.eps = prm->eps;
+  a.lambda3 = prm->lambda3;
+  a.one_minus_b1 = 1.0 - prm->beta1;
+  a.one_minus_b2 = 1.0 - prm->beta2;
+  a.bc = dbc;
+  HIP_TRY(launch_init_sol(s, a, prm->init_mode == 1 ? x0 : nullptr, prm->seed, prm->first_start, X, M, V, R, G,
+                          sol_out, feasible_out, cnt),
+          "init_sol kernels");
+  if (x_out) HIP_TRY(hipMemcpyAsync(x_out, X, sn * sizeof(double), hipMemcpyDeviceToDevice, s), "copy x_out");
+  unsigned int h = 0;
+  HIP_TRY(hipMemcpyAsync(&h, cnt, sizeof(h), hipMemcpyDeviceToHost, s), "copy feasible count");
+  HIP_TRY(hipStreamSynchronize(s), "stream synchronize");
+  if (n_feasible) *n_feasible = (int64_t)h;
+  return GRAVER_OK;
 }
 
 }  // extern "C"

@@ -1,5 +1,5 @@
 // Descent of eq. loss with Parallel Extraction (Algorithm 2) on gfx950 matrix
-// cores for large bases (n up to 1024, d up to 512).
+// cores for large bases (n up to 1024, d up to 256).
 //
 // A wave owns 16 starts; a block is 4 waves (one per SIMD) that share the
 // basis, which is streamed through LDS one 16-row block at a time (double
@@ -32,7 +32,7 @@ constexpr int kBigLogChunk = 64;
 inline int blk16(int x) { return (x + 15) / 16; }
 
 int big_db(int d) {
-  static const int sizes[] = {8, 12, 16, 20, 24, 28, 32};
+  static const int sizes[] = {8, 12, 16};
   int db = blk16(d);
   for (int s : sizes)
     if (db <= s) return s;
@@ -165,7 +165,9 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(BigArgs g, unsig
 
   for (int k = 0; k <= a.T; ++k) {
     const bool descend = k < a.T;
-    const bool needg = a.collect && k > 0 && __ballot(changed && alive) != 0;
+    // block-uniform (the row-block loop below has block barriers, and the
+    // final pass exits the loop when no wave of the block needs it)
+    const bool needg = a.collect && k > 0 && __syncthreads_or((changed && alive) ? 1 : 0) != 0;
     if (!descend && !needg) break;
     const bool bf16f = BF16F && descend;
     // rounded coordinates of the current iterate as exact bf16 operands
@@ -209,6 +211,7 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(BigArgs g, unsig
       const bool more = ib + 1 < NB;
       if (more) {
         const uint4* src = img + (size_t)(ib + 1) * kChunkU4;
+        asm volatile("" : "+v"(src));
 #pragma unroll
         for (int t = 0; t < kPerThread; ++t) pre[t] = src[threadIdx.x + t * 64 * kWaves];
       }
@@ -345,6 +348,12 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(BigArgs g, unsig
     const double bc1 = a.bc[2 * k], bc2 = a.bc[2 * k + 1];
     const float step = (float)(a.lr / bc1), ib2 = (float)(1.0 / bc2);
     int ch = 0;
+    // Opaque per-iteration copies of the base pointers: stops the compiler
+    // from hoisting every element address out of the loop (each 64-bit
+    // address would stay live in two VGPRs).
+    float* Mi = M;
+    float* Vi = V;
+    asm volatile("" : "+v"(Mi), "+v"(Vi));
     // m and v stream through registers in groups of 4 column blocks; the
     // next group's loads are issued before the current group is computed
     // (two register stages), and scheduling barriers keep the compiler from
@@ -356,8 +365,8 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(BigArgs g, unsig
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int e = base + (4 * jb + r) * 64;
-        mv[0][jb][r][0] = M[e];
-        mv[0][jb][r][1] = V[e];
+        mv[0][jb][r][0] = Mi[e];
+        mv[0][jb][r][1] = Vi[e];
       }
 #pragma unroll
     for (int gi = 0; gi < NG; ++gi) {
@@ -368,8 +377,8 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(BigArgs g, unsig
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int e = base + (4 * (4 * (gi + 1) + jj) + r) * 64;
-            mv[nx][jj][r][0] = M[e];
-            mv[nx][jj][r][1] = V[e];
+            mv[nx][jj][r][0] = Mi[e];
+            mv[nx][jj][r][1] = Vi[e];
           }
       }
 #pragma unroll
@@ -386,8 +395,8 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(BigArgs g, unsig
           ch |= (rintf(zn) != rintf(zj)) | (k == 0);
           z[jb][r] = zn;
           const int e = base + (4 * jb + r) * 64;
-          M[e] = mj;
-          V[e] = vj;
+          Mi[e] = mj;
+          Vi[e] = vj;
         }
       }
       __builtin_amdgcn_sched_barrier(0);
@@ -425,7 +434,7 @@ hipError_t launch_big_t(hipStream_t s, const BigArgs& g, unsigned long long* cou
 }  // namespace
 
 bool descent_big_supported(int n, int d) { return n <= 1024 && d <= n && big_db(d) > 0; }
-bool descent_big_bf16_supported(int d) { return big_db(d) > 0 && big_db(d) <= 24; }
+bool descent_big_bf16_supported(int d) { return big_db(d) > 0; }
 int descent_big_dbp(int d) { return big_db(d); }
 size_t big_image_bytes(int n, int d) { return (size_t)blk16(n) * big_db(d) * 64 * 32; }
 size_t big_state_floats(int d, int64_t N) { return 3 * (size_t)big_waves(N) * 4 * big_db(d) * 64; }
@@ -455,8 +464,6 @@ hipError_t launch_descent_big(hipStream_t s, const DescentArgs& a, const unsigne
       case 8: return launch_big_t<8, true>(s, g, counters);
       case 12: return launch_big_t<12, true>(s, g, counters);
       case 16: return launch_big_t<16, true>(s, g, counters);
-      case 20: return launch_big_t<20, true>(s, g, counters);
-      case 24: return launch_big_t<24, true>(s, g, counters);
     }
     return hipErrorInvalidValue;
   }
@@ -464,10 +471,6 @@ hipError_t launch_descent_big(hipStream_t s, const DescentArgs& a, const unsigne
     case 8: return launch_big_t<8, false>(s, g, counters);
     case 12: return launch_big_t<12, false>(s, g, counters);
     case 16: return launch_big_t<16, false>(s, g, counters);
-    case 20: return launch_big_t<20, false>(s, g, counters);
-    case 24: return launch_big_t<24, false>(s, g, counters);
-    case 28: return launch_big_t<28, false>(s, g, counters);
-    case 32: return launch_big_t<32, false>(s, g, counters);
   }
   return hipErrorInvalidValue;
 }

@@ -38,9 +38,11 @@ __device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
   return c;
 }
 
-// g[s, j] (stored j-major: g[j * N + s]) for start s = first + local index.
+// g[s, j] (stored j-major: g[j * N + s]) for start s = first + local index:
+// mode 0: g ~ U(l - u, u - l) (extraction starts); mode 1: x ~ U(l, u)
+// (starting points of the initial-solution search).
 __global__ void k_box_points(int n, int64_t N, const int64_t* l, const int64_t* u, uint64_t seed,
-                             int64_t first, double* g) {
+                             int64_t first, double* g, int mode) {
   int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= N) return;
   uint64_t sg = (uint64_t)(first + s);
@@ -52,11 +54,20 @@ __global__ void k_box_points(int n, int64_t N, const int64_t* l, const int64_t* 
       if (j >= n) break;
       uint32_t wa = h ? w.z : w.x, wb = h ? w.w : w.y;
       double U = ((double)(wa >> 5) * 67108864.0 + (double)(wb >> 6)) * (1.0 / 9007199254740992.0);
-      double lo = (double)(l[j] - u[j]);
-      double width = (double)(2 * (u[j] - l[j]));
+      double lo = mode ? (double)l[j] : (double)(l[j] - u[j]);
+      double width = mode ? (double)(u[j] - l[j]) : (double)(2 * (u[j] - l[j]));
       g[(size_t)j * N + s] = lo + U * width;
     }
   }
+}
+
+// X[s, j] = G[j * N + s] (j-major to row-major).
+__global__ void k_transpose_f64(int n, int64_t N, const double* G, double* X) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N * n) return;
+  int64_t s = t / n;
+  int j = (int)(t % n);
+  X[t] = G[(size_t)j * N + s];
 }
 
 // z[s, i] = sum_j P[i, j] g[s, j], ascending j from 0.0; z row-major N x d.
@@ -76,7 +87,7 @@ hipError_t launch_init_box(hipStream_t s, int n, int d, int64_t N, const double*
                            double* g_scratch, double* z_out) {
   unsigned blocks = (unsigned)((N + 255) / 256);
   hipLaunchKernelGGL(k_box_points, dim3(blocks), dim3(256), 0, s, n, N, l, u, seed, first_start,
-                     g_scratch);
+                     g_scratch, 0);
   hipLaunchKernelGGL(k_project, dim3(blocks), dim3(256), 0, s, n, d, N, P, g_scratch, z_out);
   return hipGetLastError();
 }
@@ -179,6 +190,82 @@ hipError_t launch_descent_fp64(hipStream_t s, const DescentArgs& a, double* z, d
   unsigned blocks = (unsigned)((a.N + 63) / 64);
   hipLaunchKernelGGL(k_descent_fp64, dim3(blocks), dim3(64), 0, s, a, z, m, v, rprev, sign_scratch,
                      key_scratch, pool, counters);
+  return hipGetLastError();
+}
+
+// ---- initial feasible solutions (eq. init_sol) ---------------------------
+// One thread per start, binary64 with the oracle's operation order:
+//   res_i = (sum_j A_ij x_j) - b_i,  grad_j = 2 (sum_i A_ij res_i)
+//           + lam3 ((ceil x_j + floor x_j) - 2 x_j),
+// Adam, then projection onto [l, u]; finally r = round(x) and the exact
+// test A r = b, l <= r <= u.  X, M, V are row-major S x n, R is S x m.
+__global__ void k_init_sol(InitArgs a, double* __restrict__ X, double* __restrict__ M, double* __restrict__ V,
+                           double* __restrict__ R, int64_t* __restrict__ xr, int32_t* __restrict__ feas,
+                           unsigned int* nfeas) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= a.S) return;
+  const int n = a.n, m = a.m;
+  double* x = X + (size_t)s * n;
+  double* mm = M + (size_t)s * n;
+  double* vv = V + (size_t)s * n;
+  double* res = R + (size_t)s * m;
+  for (int k = 0; k < a.T; ++k) {
+    for (int i = 0; i < m; ++i) {
+      double acc = 0.0;
+      for (int j = 0; j < n; ++j) acc = acc + (double)a.A[(size_t)i * n + j] * x[j];
+      res[i] = acc - (double)a.b[i];
+    }
+    const double bc1 = a.bc[2 * k], bc2 = a.bc[2 * k + 1];
+    for (int j = 0; j < n; ++j) {
+      double g = 0.0;
+      for (int i = 0; i < m; ++i) g = g + (double)a.A[(size_t)i * n + j] * res[i];
+      const double xj = x[j];
+      double t = ceil(xj) + floor(xj);
+      t = t - 2.0 * xj;
+      const double grad = 2.0 * g + a.lambda3 * t;
+      const double mj = a.beta1 * mm[j] + a.one_minus_b1 * grad;
+      const double vj = a.beta2 * vv[j] + a.one_minus_b2 * (grad * grad);
+      mm[j] = mj;
+      vv[j] = vj;
+      const double mhat = mj / bc1;
+      const double vhat = vj / bc2;
+      double xn = xj - (a.lr * mhat) / (sqrt(vhat) + a.eps);
+      xn = fmin(fmax(xn, (double)a.l[j]), (double)a.u[j]);
+      x[j] = xn;
+    }
+  }
+  bool ok = true;
+  int64_t* r = xr + (size_t)s * n;
+  for (int j = 0; j < n; ++j) {
+    const int64_t v = (int64_t)rint(x[j]);
+    r[j] = v;
+    ok = ok && v >= a.l[j] && v <= a.u[j];
+  }
+  for (int i = 0; i < m && ok; ++i) {
+    int64_t acc = 0;
+    for (int j = 0; j < n; ++j) acc += a.A[(size_t)i * n + j] * r[j];
+    ok = acc == a.b[i];
+  }
+  feas[s] = ok ? 1 : 0;
+  if (ok) atomicAdd(nfeas, 1u);
+}
+
+hipError_t launch_init_sol(hipStream_t s, const InitArgs& a, const double* x0, uint64_t seed, int64_t first,
+                           double* X, double* M, double* V, double* R, double* gscratch, int64_t* xr,
+                           int32_t* feas, unsigned int* nfeas) {
+  const unsigned blocks = (unsigned)((a.S + 63) / 64);
+  if (x0) {
+    hipMemcpyAsync(X, x0, (size_t)a.S * a.n * sizeof(double), hipMemcpyDeviceToDevice, s);
+  } else {
+    hipLaunchKernelGGL(k_box_points, dim3((unsigned)((a.S + 255) / 256)), dim3(256), 0, s, a.n, a.S, a.l, a.u,
+                       seed, first, gscratch, 1);
+    hipLaunchKernelGGL(k_transpose_f64, dim3((unsigned)((a.S * a.n + 255) / 256)), dim3(256), 0, s, a.n, a.S,
+                       gscratch, X);
+  }
+  hipMemsetAsync(M, 0, (size_t)a.S * a.n * sizeof(double), s);
+  hipMemsetAsync(V, 0, (size_t)a.S * a.n * sizeof(double), s);
+  hipMemsetAsync(nfeas, 0, sizeof(unsigned int), s);
+  hipLaunchKernelGGL(k_init_sol, dim3(blocks), dim3(64), 0, s, a, X, M, V, R, xr, feas, nfeas);
   return hipGetLastError();
 }
 

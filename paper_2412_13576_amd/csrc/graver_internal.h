@@ -33,7 +33,10 @@ enum Slot : int {
   WS_A_R, WS_A_PART, WS_A_DONE, WS_A_QG, WS_A_TAB, WS_A_PX, WS_A_STEPS,
   WS_MF_B, WS_MF_BT, WS_MF_STATE, WS_MISC,
   WS_F_CODE, WS_F_HIST, WS_F_OFF, WS_F_CUR, WS_F_BL, WS_A_QFLAG, WS_LOG, WS_LOG_COUNT, WS_MF_BAK, WS_MISC2,
+  WS_I_X, WS_I_M, WS_I_V, WS_I_R, WS_I_G,
+  WS_END
 };
+static_assert(WS_END <= graver_ctx::kSlots, "too many workspace slots");
 void* ws_get(graver_ctx* ctx, int slot, size_t bytes, graver_status* st);
 
 graver_status kernel_basis_host(int32_t m, int32_t n, const int64_t* A, int32_t do_lll,
@@ -76,6 +79,20 @@ struct DescentArgs {
   int32_t lim_uniform;  // u_i - l_i when equal for every i, else -1
   LogDev log;           // MFMA path: candidate log
 };
+
+struct InitArgs {
+  int32_t m, n, T;
+  int64_t S;
+  const int64_t* A;
+  const int64_t* b;
+  const int64_t* l;
+  const int64_t* u;
+  double lr, beta1, beta2, eps, lambda3, one_minus_b1, one_minus_b2;
+  const double* bc;
+};
+hipError_t launch_init_sol(hipStream_t s, const InitArgs& a, const double* x0, uint64_t seed, int64_t first,
+                           double* X, double* M, double* V, double* R, double* gscratch, int64_t* xr,
+                           int32_t* feas, unsigned int* nfeas);
 
 hipError_t launch_init_box(hipStream_t s, int n, int d, int64_t N, const double* P,
                            const int64_t* l, const int64_t* u, uint64_t seed,

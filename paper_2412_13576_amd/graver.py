@@ -24,7 +24,7 @@ STATUS = {0: "OK", -1: "E_INVALID", -2: "E_INFEASIBLE_START", -3: "E_NOT_KERNEL"
 
 EXPORTED = ["graver_ctx_create", "graver_ctx_destroy", "graver_ctx_set_stream", "graver_last_error",
             "graver_status_string", "graver_kernel_basis", "graver_extract", "graver_filter",
-            "graver_augment"]
+            "graver_augment", "graver_init_solutions"]
 
 
 class GraverError(RuntimeError):
@@ -71,6 +71,12 @@ class AugmentParams(C.Structure):
     _fields_ = [("max_steps", C.c_int64)]
 
 
+class InitParams(C.Structure):
+    _fields_ = [("n_starts", C.c_int64), ("iters", C.c_int32), ("init_mode", C.c_int32),
+                ("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
+                ("lambda3", C.c_double), ("seed", C.c_uint64), ("first_start", C.c_int64)]
+
+
 _lib = None
 
 
@@ -99,8 +105,11 @@ def lib():
         L.graver_augment.argtypes = [C.c_void_p, C.POINTER(Problem), C.POINTER(ObjectiveC), C.c_void_p,
                                      C.c_int64, C.c_int32, C.c_void_p, C.POINTER(AugmentParams),
                                      C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]
+        L.graver_init_solutions.argtypes = [C.c_void_p, C.POINTER(Problem), C.POINTER(InitParams),
+                                            C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                            C.POINTER(C.c_int64)]
         for name in ("graver_ctx_create", "graver_ctx_set_stream", "graver_kernel_basis",
-                     "graver_extract", "graver_filter", "graver_augment"):
+                     "graver_extract", "graver_filter", "graver_augment", "graver_init_solutions"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -173,7 +182,7 @@ class DeviceProblem:
 
     def c(self) -> Problem:
         m, n = self.A.shape
-        d = self.B.shape[1]
+        d = 0 if self.B is None else self.B.shape[1]
         return Problem(m, n, d, _ptr(self.A), _ptr(self.b), _ptr(self.l), _ptr(self.u), _ptr(self.B),
                        _ptr(self.P))
 
@@ -246,3 +255,27 @@ def augment(ctx: Context, prob: DeviceProblem, obj, dirs, x_starts, max_steps: i
                                 dirs.shape[0], S, x_starts.data_ptr(), C.byref(prm), x_out.data_ptr(),
                                 f_out.data_ptr(), steps.data_ptr(), C.byref(best)))
     return x_out, f_out, steps, best.value
+
+
+def init_params(n_starts, iters, init_mode=0, seed=0, first_start=0, lr=0.003, beta1=0.9, beta2=0.999,
+                eps=1e-8, lambda3=0.1) -> InitParams:
+    return InitParams(n_starts, iters, init_mode, lr, beta1, beta2, eps, lambda3, seed, first_start)
+
+
+def init_solutions(ctx: Context, prob: DeviceProblem, params: InitParams, x0=None):
+    """graver_init_solutions.  Returns (x_final float64 S x n, rounded int64
+    S x n, feasible int32 S) device tensors and the feasible count."""
+    import torch
+    S = params.n_starts
+    n = prob.A.shape[1]
+    dev = prob.A.device
+    x_out = torch.empty((S, n), dtype=torch.float64, device=dev)
+    sol = torch.empty((S, n), dtype=torch.int64, device=dev)
+    feas = torch.empty(S, dtype=torch.int32, device=dev)
+    if x0 is not None:
+        x0 = x0.contiguous()
+    cnt = C.c_int64(0)
+    pc = prob.c()
+    _check(lib().graver_init_solutions(ctx.h, C.byref(pc), C.byref(params), _ptr(x0), x_out.data_ptr(),
+                                       sol.data_ptr(), feas.data_ptr(), C.byref(cnt)))
+    return x_out, sol, feas, cnt.value

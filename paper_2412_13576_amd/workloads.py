@@ -159,6 +159,29 @@ def sparse_quadratic_instance(seed: int, n: int, m: int) -> Instance:
                     meta=dict(law="mix", seed=seed))
 
 
+def identity_block_instance(seed: int, n: int, m: int, density: float = 0.2) -> Instance:
+    """Large-shape instance with an identity block: A = [I_m | C], C with
+    entries 0 w.p. 1 - density else uniform in {+-1, +-2}; x0 uniform
+    integers in [-2, 2]; l = -5, u = 5; quadratic f with Q = M^T M
+    (M iid uniform in [-2, 2]) and c iid uniform in [-5, 5].  The identity
+    block keeps the integer kernel basis computation cheap at large n."""
+    rng = _rng(seed)
+    d = n - m
+    nz = rng.random((m, d)) < density
+    mag = rng.integers(1, 3, size=(m, d))
+    sg = np.where(rng.random((m, d)) < 0.5, -1, 1)
+    C = (nz * mag * sg).astype(np.int64)
+    A = np.concatenate([np.eye(m, dtype=np.int64), C], axis=1)
+    x0 = rng.integers(-2, 3, size=n, dtype=np.int64)
+    M = rng.integers(-2, 3, size=(n, n), dtype=np.int64)
+    Q = (M.T @ M).astype(np.float64)
+    c = rng.integers(-5, 6, size=n, dtype=np.int64).astype(np.float64)
+    return Instance(name=f"idblock_m{m}_n{n}_s{seed}", A=A, b=A @ x0,
+                    l=np.full(n, -5, np.int64), u=np.full(n, 5, np.int64),
+                    x0=x0, f_kind="quadratic", Q=Q, c=c,
+                    meta=dict(law="identity_block", seed=seed))
+
+
 def random_instance(seed: int, m: int, n: int, lo: int = -3, hi: int = 3,
                     bound: int = 5, density: float = 1.0) -> Instance:
     """Small random instance for tests: A iid uniform integers in [lo, hi]
