@@ -18,6 +18,7 @@ oracle (plain binary64 numpy) timed on a bounded sample on this host.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -31,6 +32,38 @@ sys.path.insert(0, ROOT)
 PEAK_FP32_MFMA = 157.3  # TFLOP/s, MI355X dense FP32 matrix
 PEAK_HBM = 8000.0       # GB/s
 
+# HBM traffic of the descent kernel, from two rocprofv3 --pmc runs
+# (FETCH_SIZE, WRITE_SIZE) scaled by the same counters on a copy of known
+# size.  The summary records a hash of the kernel's sources; a figure taken
+# on other sources is not reported.
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_descent_f32_qp_m20_n100_hbm_traffic.md")
+KERNEL_SOURCES = ["paper_2412_13576_amd/csrc/descent_f32.hip", "paper_2412_13576_amd/csrc/graver_internal.h",
+                  "paper_2412_13576_amd/csrc/pool_device.h"]
+
+
+def kernel_sources_sha256() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def _measured_traffic(N, T, precision):
+    """Bytes per descent launch recorded for these sources and this launch
+    shape, or None."""
+    try:
+        with open(TRAFFIC_PROFILE) as fh:
+            kv = dict(line.split(":", 1) for line in fh if ":" in line and not line.startswith(("#", "|", "`")))
+    except OSError:
+        return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("source_sha256") != kernel_sources_sha256():
+        return None
+    if kv.get("launch") != f"N={N} T={T} {precision}":
+        return None
+    return float(kv["hbm_bytes_per_launch"])
+
 
 def _cpu_baseline(inst, B, P, T, seconds_target=15.0):
     """Oracle (binary64 numpy, one core) on a bounded sample of starts at the
@@ -38,7 +71,7 @@ def _cpu_baseline(inst, B, P, T, seconds_target=15.0):
     from oracle import philox
     from oracle import surrogate as S
 
-    n_sample = 64
+    n_sample = 384
     _, z0 = philox.box_starts(P, inst.l, inst.u, n_sample, seed=99)
     t = time.perf_counter()
     iters = T
@@ -143,7 +176,7 @@ def main():
         "aug_mean_steps": float(recs[-1][4].double().mean().item()),
         "roofline": {"bound": "mfma", "kernel": "k_descent_f32", "achieved": achieved,
                      "peak": PEAK_FP32_MFMA, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA,
-                     "traffic": None,
+                     "traffic": _measured_traffic(N, T, args.precision),
                      "algorithmic": "4*n*d flop per start-iteration (B z forward + B^T sign backward)"},
     }
     if not args.no_cpu_baseline:

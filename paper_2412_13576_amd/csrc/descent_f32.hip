@@ -31,7 +31,9 @@
 // so binary32 accumulation is exact.  A start whose iterate leaves that
 // range stops collecting (counted as out of range).  When a start's r
 // changed and g is nonzero and inside [l - u, u - l], its int8 key is
-// assembled in LDS and inserted into the device pool.
+// assembled in LDS and appended to the candidate log (each wave reserves
+// 64-row chunks with one atomic); a separate kernel moves the log into the
+// device pool, which removes duplicates.
 #include <hip/hip_runtime.h>
 
 #include "graver_internal.h"
