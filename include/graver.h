@@ -231,6 +231,56 @@ graver_status graver_init_solutions(graver_ctx* ctx, const graver_problem* prob,
                                     double* x_out, int64_t* sol_out, int32_t* feasible_out,
                                     int64_t* n_feasible);
 
+/* ---- end-to-end solve (MAPE, Section 3.3) ----------------------------- */
+
+typedef struct {
+  graver_extract_params extract; /* Algorithm 2; collect must be 1; init_mode
+                                    0 draws starts with P (computed by the
+                                    library when prob->B is NULL)            */
+  graver_init_params init;       /* eq. init_sol starting points             */
+  int64_t max_steps;             /* augmentation cap per start (>= 0)        */
+  int32_t lll;                   /* library-computed basis: LLL-reduce it    */
+  const int64_t* x_starts;       /* device, n_x_starts x n: feasible points
+                                    the caller already has, augmented after
+                                    the initial solutions (may be NULL)     */
+  int32_t n_x_starts;
+  int32_t reuse;                 /* 1: look up / keep the basis and the
+                                    filtered set of this (A, u - l) in the
+                                    context (Section 3.3: the Graver basis
+                                    depends on A only, so instances sharing A
+                                    reuse one extraction)                    */
+} graver_solve_params;
+
+typedef struct {
+  int32_t d;                 /* kernel dimension n - rank(A)                 */
+  int32_t reused;            /* 1 when the cached set was used               */
+  int32_t best_start;        /* index of the best start among the feasible ones */
+  int64_t unique;            /* distinct verified candidates (0 when reused) */
+  int64_t filtered;          /* size of the filtered direction set F         */
+  int64_t feasible_starts;   /* feasible rounded initial solutions           */
+  int64_t augment_steps;     /* moves made over all starts                   */
+  double ms_basis, ms_extract, ms_filter, ms_init, ms_augment; /* host wall time per phase */
+} graver_solve_stats;
+
+/* MAPE end to end: kernel basis (Lemma 3.1, Theorem 3.2; host, or the
+ * caller's prob->B / prob->P), Parallel Extraction (Algorithm 2), the
+ * minimality filter, initial feasible solutions (eq. init_sol), and
+ * augmentation (Algorithm 1) from every feasible initial solution, in the
+ * order found, then from the caller's x_starts, with directions F u (-F);
+ * the best end point is the answer (ties: the lowest start index).
+ * prob: device pointers A, b, l, u; B (n x d) and P (d x n) may be NULL.
+ * Outputs: x_best (device, n int64), *f_best (host), stats (host, may be
+ * NULL).  GRAVER_E_INFEASIBLE_START when there is no start at all (no
+ * feasible initial solution and no x_starts) or an x_starts row violates
+ * A x = b or l <= x <= u.
+ * With reuse, the context keeps the basis and F of each distinct (A, u - l)
+ * until it is destroyed; a later call with the same (A, u - l) skips the
+ * basis, the extraction and the filter (its extraction parameters are then
+ * not used). */
+graver_status graver_solve(graver_ctx* ctx, const graver_problem* prob, const graver_objective* f,
+                           const graver_solve_params* params, int64_t* x_best, double* f_best,
+                           graver_solve_stats* stats);
+
 #ifdef __cplusplus
 }
 #endif

@@ -32,6 +32,7 @@ SOURCES = {
     "descent_big.hip": ["-ffp-contract=fast"],
     "filter.hip": [],
     "augment.hip": ["-ffp-contract=off"],
+    "solve.cpp": ["-x", "hip"],
 }
 
 

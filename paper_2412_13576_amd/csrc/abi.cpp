@@ -157,6 +157,7 @@ void graver_ctx_destroy(graver_ctx* ctx) {
   hipStreamSynchronize(ctx->stream);
   for (int i = 0; i < graver_ctx::kSlots; ++i)
     if (ctx->buf[i]) hipFree(ctx->buf[i]);
+  solve_cache_free(ctx);
   delete ctx;
 }
 
@@ -321,7 +322,7 @@ graver_status graver_extract(graver_ctx* ctx, const graver_problem* prob,
     } else {
       const bool small = descent_f32_supported(n, d);
       if (!small && !descent_big_supported(n, d))
-        return set_error(GRAVER_E_INVALID, "the MFMA descent supports n <= 1024 and d <= 256 in this build");
+        return set_error(GRAVER_E_INVALID, "the MFMA descent supports n <= 1024 and d <= 1024");
       // |B_ij| <= 256 makes every bf16 operand exact; row l1 norms bound the
       // exact range of the candidate map.
       int* rowl1 = (int*)ws_get(ctx, WS_MISC, 64, &st);
@@ -346,6 +347,9 @@ graver_status graver_extract(graver_ctx* ctx, const graver_problem* prob,
       HIP_TRY(hipStreamSynchronize(s), "sync");
       if (hrow[1] > 256)
         return set_error(GRAVER_E_INVALID, "the MFMA descent needs |B_ij| <= 256 (exact bf16 operands)");
+      // large bases: candidates B r with |r_j| <= 256 must stay exact in fp32
+      if (!small && (int64_t)hrow[0] * 256 >= (int64_t)1 << 24)
+        return set_error(GRAVER_E_INVALID, "the MFMA descent needs every row l1 norm of B below 65536");
       const float zrange = (float)std::min(1073741824.0, std::floor(16777216.0 / std::max(hrow[0], 1)));
       const int DBlay = small ? (d + 15) / 16 : descent_big_dbp(d);
       const size_t sfloats = small ? f32_state_floats(n, d, N) : big_state_floats(d, N);

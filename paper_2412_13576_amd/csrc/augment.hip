@@ -291,6 +291,23 @@ __global__ void k_best(int S, const double* f, int32_t* best) {
   *best = b;
 }
 
+// dst[r, :] = src[idx[r], :] for r < cnt (int64 rows of n).
+__global__ void k_gather_rows_i64(const int64_t* src, int n, const int32_t* idx, int64_t cnt, int64_t* dst) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= cnt * n) return;
+  const int64_t r = t / n;
+  const int j = (int)(t % n);
+  dst[t] = src[(size_t)idx[r] * n + j];
+}
+
+hipError_t launch_gather_rows_i64(hipStream_t s, const int64_t* src, int n, const int32_t* idx, int64_t cnt,
+                                  int64_t* dst) {
+  if (cnt > 0)
+    hipLaunchKernelGGL(k_gather_rows_i64, dim3((unsigned)((cnt * n + 255) / 256)), dim3(256), 0, s, src, n, idx,
+                       cnt, dst);
+  return hipGetLastError();
+}
+
 graver_status run_augment(graver_ctx* ctx, const AugArgs& a, const int64_t* x_starts, int64_t* x_out,
                           double* f_out, int64_t* steps_out, int32_t* best_out) {
   hipStream_t s = ctx->stream;

@@ -1,20 +1,30 @@
 // Descent of eq. loss with Parallel Extraction (Algorithm 2) on gfx950 matrix
-// cores for large bases (n up to 1024, d up to 256).
+// cores for large bases (n up to 1024, d up to 1024).
 //
-// A wave owns 16 starts; a block is 4 waves (one per SIMD) that share the
-// basis, which is streamed through LDS one 16-row block at a time (double
-// buffered, the next block prefetched into registers while the current one
-// is used).  z and the gradient accumulators stay in registers; m and v are
-// read and written once per iteration in the wave-native layout.  Per row
-// block ib the wave computes
-//   y_ib   = B_ib z                      (binary32 MFMA, or bf16 hi/lo split)
+// A start group is 16 starts.  Its coordinates are split over CS waves of a
+// block (column slices of DBPW 16-column blocks each), so the per-wave
+// register state stays bounded as d grows; a block is 4 waves (one per
+// SIMD), i.e. 4 / CS start groups.  The basis is streamed through LDS one
+// 16-row block at a time (double buffered, the next block prefetched into
+// registers while the current one is used).  z and the gradient
+// accumulators stay in registers; m and v are read and written once per
+// iteration in the wave-native layout.  Per row block ib each wave computes
+//   y_ib   = B_ib z      over its own columns (binary32 MFMA, or the bf16
+//                        hi/lo split), summed over the slices through LDS
 //   G     += B_ib^T sign(y_ib)           (exact bf16 operands, fp32 sums)
-//   g_ib   = B_ib r   for the previous iterate r = round(z)   (exact bf16)
+//   g_ib   = B_ib r      for the previous iterate r = round(z) (exact bf16
+//                        operands, integer partial sums, summed over slices)
 // so the exact candidate of iterate t is formed during iteration t+1 (and a
-// final pass forms the last one).  Rounded coordinates beyond |r| <= 256 are
-// not exact bf16 operands: such an iterate yields no candidate (counted as
-// out of range).  Candidate rows are staged per start in a global scratch
-// row, and rows that pass the box test are appended to the candidate log.
+// final pass forms the last one).  The infinity norm, its ties, the change
+// flag and the exact-range flag of a start are combined over its slices
+// once per iteration.  Rounded coordinates beyond |r| <= 256 are not exact
+// bf16 operands: such an iterate yields no candidate (counted as out of
+// range).  The first slice of a start group stages candidate rows in a
+// global scratch row and appends those that pass the box test to the
+// candidate log.
+//
+// The LDS image of a row block holds B as bf16 only (every |B_ij| <= 256 is
+// exact in bf16); the binary32 forward widens the operands in registers.
 #include <hip/hip_runtime.h>
 
 #include "graver_internal.h"
@@ -31,12 +41,19 @@ constexpr int kBigLogChunk = 64;
 
 inline int blk16(int x) { return (x + 15) / 16; }
 
-int big_db(int d) {
-  static const int sizes[] = {8, 12, 16};
-  int db = blk16(d);
-  for (int s : sizes)
-    if (db <= s) return s;
-  return -1;
+// Column split: CS waves per start group, DBPW column blocks per wave.
+struct BigShape {
+  int cs, dbpw;
+};
+
+BigShape big_shape(int d) {
+  const int db = blk16(d);
+  static const int kCs[] = {1, 2, 4};
+  static const int kPerWave[] = {8, 12, 16};
+  for (int cs : kCs)
+    for (int w : kPerWave)
+      if (cs * w >= db) return {cs, w};
+  return {0, 0};
 }
 
 inline int64_t big_waves(int64_t N) {
@@ -72,25 +89,22 @@ __device__ __forceinline__ int xand4(int x) {
   return x & __shfl_xor(x, 32, 64);
 }
 
-// Per row block ib (16 rows), for DBP column blocks:
-//   FA[jb*64 + l] float4 (B[16ib + l%16][16jb + 4(l/16) + r])
-//   FB[jb*64 + l] 4 x bf16, same entries
+// Per row block ib (16 rows), for DBT column blocks:
+//   FB[jb*64 + l] 4 x bf16 (B[16ib + l%16][16jb + 4(l/16) + r])
 //   BT[jb*64 + l] 4 x bf16 (B[16ib + 4(l/16) + r][16jb + l%16])
-// laid out as [FA | FB | BT], chunk_bytes = DBP * 64 * 32 bytes.
-__global__ void k_pack_big(int n, int d, int NB, int DBP, const int64_t* B, unsigned char* img) {
+// laid out as [FB | BT], chunk_bytes = DBT * 64 * 16 bytes.
+__global__ void k_pack_big(int n, int d, int NB, int DBT, const int64_t* B, unsigned char* img) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
-  int per = DBP * 64;
+  int per = DBT * 64;
   if (t >= NB * per) return;
   int ib = t / per, rest = t % per, jb = rest / 64, l = rest % 64;
-  unsigned char* chunk = img + (size_t)ib * per * 32;
-  float* FA = reinterpret_cast<float*>(chunk);
-  short* FB = reinterpret_cast<short*>(chunk + (size_t)per * 16);
-  short* BT = reinterpret_cast<short*>(chunk + (size_t)per * 24);
+  unsigned char* chunk = img + (size_t)ib * per * 16;
+  short* FB = reinterpret_cast<short*>(chunk);
+  short* BT = reinterpret_cast<short*>(chunk + (size_t)per * 8);
   int i = 16 * ib + l % 16;
   for (int r = 0; r < 4; ++r) {
     int j = 16 * jb + 4 * (l / 16) + r;
     int64_t b = (i < n && j < d) ? B[(size_t)i * d + j] : 0;
-    FA[(size_t)rest * 4 + r] = (float)b;
     FB[(size_t)rest * 4 + r] = (short)(__float_as_uint((float)b) >> 16);
   }
   int j2 = 16 * jb + l % 16;
@@ -117,35 +131,45 @@ __device__ __forceinline__ void zero_rows_big(const LogDev& log, uint32_t first,
   for (uint32_t t = lane; t < rows * (uint32_t)dw; t += 64) base[t] = 0u;
 }
 
-template <int DBP, bool BF16F>
+template <int CS, int DBPW, bool BF16F>
 __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(BigArgs g, unsigned long long* counters) {
   const DescentArgs& a = g.a;
-  constexpr int kChunkBytes = DBP * 64 * 32;
-  constexpr int kChunkU4 = kChunkBytes / 16;               // uint4 per chunk
-  constexpr int kPerThread = kChunkU4 / (64 * kWaves);     // DBP * 2
+  constexpr int DBT = CS * DBPW;                        // column blocks of the image
+  constexpr int kChunkU4 = DBT * 64;                    // uint4 per row-block chunk
+  constexpr int kPerThread = kChunkU4 / (64 * kWaves);  // DBT / 4
   extern __shared__ __align__(16) unsigned char smem[];
   uint4* buf0 = reinterpret_cast<uint4*>(smem);
   uint4* buf1 = buf0 + kChunkU4;
   int* sLim = reinterpret_cast<int*>(buf1 + kChunkU4);
+  // slice partial sums (forward, candidate) and the per-iteration exchange
+  __shared__ floatx4 redY[CS > 1 ? kWaves : 1][64];
+  __shared__ floatx4 redG[CS > 1 ? kWaves : 1][64];
+  __shared__ float xmu[kWaves][16], xcnt[kWaves][16];
+  __shared__ int xflag[kWaves][16];
 
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int q = lane >> 4, sl = lane & 15;
-  const int64_t w = (int64_t)blockIdx.x * kWaves + wid;
-  const int64_t sidx = w * 16 + sl;
+  const int cs = wid % CS;       // column slice of this wave
+  const int gw0 = wid - cs;      // first wave of this start group
+  const bool lead = cs == 0;     // the slice that emits candidates
+  const int64_t sgroup = (int64_t)blockIdx.x * (kWaves / CS) + wid / CS;
+  const int64_t w = (int64_t)blockIdx.x * kWaves + wid;  // = sgroup * CS + cs
+  const int64_t sidx = sgroup * 16 + sl;
   const bool svalid = sidx < a.N;
   const int NB = g.NB;
   const int stride = g.stride;
+  const int jb0 = cs * DBPW;     // first image column block of this wave
   for (int i = threadIdx.x; i < 16 * NB; i += blockDim.x) sLim[i] = i < a.n ? (int)(a.u[i] - a.l[i]) : 0;
 
-  float z[DBP][4];
+  float z[DBPW][4];
   // per-wave base pointers (uniform) with 32-bit lane offsets
-  const size_t wbase = (size_t)w * 4 * DBP * 64;
+  const size_t wbase = (size_t)w * 4 * DBPW * 64;
   float* Z = g.z + wbase;
   float* M = g.z + g.per + wbase;
   float* V = g.z + 2 * g.per + wbase;
   const int base = lane;
 #pragma unroll
-  for (int jb = 0; jb < DBP; ++jb)
+  for (int jb = 0; jb < DBPW; ++jb)
 #pragma unroll
     for (int r = 0; r < 4; ++r) z[jb][r] = Z[base + (4 * jb + r) * 64];
 
@@ -165,29 +189,65 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(BigArgs g, unsig
 
   for (int k = 0; k <= a.T; ++k) {
     const bool descend = k < a.T;
+    // infinity norm and its ties, change and exact-range flags of the
+    // current iterate, over this wave's coordinates, then over the slices
+    float mu = 0.f;
+#pragma unroll
+    for (int jb = 0; jb < DBPW; ++jb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) mu = fmaxf(mu, fabsf(z[jb][r]));
+    mu = xmax4(mu);
+    float cnt = 0.f;
+    int inrange = 1;
+#pragma unroll
+    for (int jb = 0; jb < DBPW; ++jb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        cnt += fabsf(z[jb][r]) == mu ? 1.f : 0.f;
+        inrange &= fabsf(rintf(z[jb][r])) <= 256.f;
+      }
+    cnt = xsum4(cnt);
+    inrange = xand4(inrange);
+    if constexpr (CS > 1) {
+      if (q == 0) {
+        xmu[wid][sl] = mu;
+        xcnt[wid][sl] = cnt;
+        xflag[wid][sl] = (changed ? 1 : 0) | (inrange ? 2 : 0);
+      }
+      __syncthreads();
+      float gm = xmu[gw0][sl];
+#pragma unroll
+      for (int c = 1; c < CS; ++c) gm = fmaxf(gm, xmu[gw0 + c][sl]);
+      float gc = 0.f;
+      int f_or = 0, f_and = 2;
+#pragma unroll
+      for (int c = 0; c < CS; ++c) {
+        if (xmu[gw0 + c][sl] == gm) gc += xcnt[gw0 + c][sl];
+        const int f = xflag[gw0 + c][sl];
+        f_or |= f & 1;
+        f_and &= f & 2;
+      }
+      mu = gm;
+      cnt = gc;
+      changed = f_or;
+      inrange = f_and ? 1 : 0;
+    }
     // block-uniform (the row-block loop below has block barriers, and the
     // final pass exits the loop when no wave of the block needs it)
     const bool needg = a.collect && k > 0 && __syncthreads_or((changed && alive) ? 1 : 0) != 0;
     if (!descend && !needg) break;
-    const bool bf16f = BF16F && descend;
     // rounded coordinates of the current iterate as exact bf16 operands
-    shortx4 rp[DBP];
-    int inrange = 1;
+    shortx4 rp[DBPW];
     if (needg) {
 #pragma unroll
-      for (int jb = 0; jb < DBP; ++jb)
+      for (int jb = 0; jb < DBPW; ++jb)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const float rv = rintf(z[jb][r]);
-          inrange &= fabsf(rv) <= 256.f;
-          rp[jb][r] = int_bf16(rv);
-        }
-      inrange = xand4(inrange);
+        for (int r = 0; r < 4; ++r) rp[jb][r] = int_bf16(rintf(z[jb][r]));
     }
-    shortx4 hi[BF16F ? DBP : 1], lo[BF16F ? DBP : 1];
+    shortx4 hi[BF16F ? DBPW : 1], lo[BF16F ? DBPW : 1];
     if constexpr (BF16F) {
 #pragma unroll
-      for (int jb = 0; jb < DBP; ++jb)
+      for (int jb = 0; jb < DBPW; ++jb)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           short h = bf16_rne(z[jb][r]);
@@ -195,9 +255,9 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(BigArgs g, unsig
           lo[jb][r] = bf16_rne(z[jb][r] - bf16_to_f(h));
         }
     }
-    floatx4 G[DBP];
+    floatx4 G[DBPW];
 #pragma unroll
-    for (int jb = 0; jb < DBP; ++jb) G[jb] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int jb = 0; jb < DBPW; ++jb) G[jb] = floatx4{0.f, 0.f, 0.f, 0.f};
     int inbox = 1, nonzero = 0;
 
     // stage row block 0
@@ -215,16 +275,16 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(BigArgs g, unsig
 #pragma unroll
         for (int t = 0; t < kPerThread; ++t) pre[t] = src[threadIdx.x + t * 64 * kWaves];
       }
-      const floatx4* FA = reinterpret_cast<const floatx4*>(cur);
-      const shortx4* FB = reinterpret_cast<const shortx4*>(reinterpret_cast<unsigned char*>(cur) + DBP * 64 * 16);
-      const shortx4* BT = reinterpret_cast<const shortx4*>(reinterpret_cast<unsigned char*>(cur) + DBP * 64 * 24);
+      const shortx4* FB = reinterpret_cast<const shortx4*>(cur) + jb0 * 64;
+      const shortx4* BT = reinterpret_cast<const shortx4*>(cur) + (DBT + jb0) * 64;
+      floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
+      floatx4 gx = floatx4{0.f, 0.f, 0.f, 0.f};
       if (descend) {
-        floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
         // column blocks in groups of 4 with scheduling barriers in between:
         // bounds the number of LDS operands loaded ahead (register pressure)
         if constexpr (BF16F) {
 #pragma unroll
-          for (int jg = 0; jg < DBP; jg += 4) {
+          for (int jg = 0; jg < DBPW; jg += 4) {
 #pragma unroll
             for (int jb = jg; jb < jg + 4; ++jb) {
               const shortx4 A = FB[jb * 64 + lane];
@@ -235,21 +295,50 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(BigArgs g, unsig
           }
         } else {
 #pragma unroll
-          for (int jg = 0; jg < DBP; jg += 4) {
+          for (int jg = 0; jg < DBPW; jg += 4) {
 #pragma unroll
             for (int jb = jg; jb < jg + 4; ++jb) {
-              const floatx4 A = FA[jb * 64 + lane];
+              const shortx4 A = FB[jb * 64 + lane];
 #pragma unroll
-              for (int r = 0; r < 4; ++r) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A[r], z[jb][r], acc, 0, 0, 0);
+              for (int r = 0; r < 4; ++r)
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(bf16_to_f(A[r]), z[jb][r], acc, 0, 0, 0);
             }
             __builtin_amdgcn_sched_barrier(0);
           }
         }
+      }
+      if (needg) {
+#pragma unroll
+        for (int jg = 0; jg < DBPW; jg += 4) {
+#pragma unroll
+          for (int jb = jg; jb < jg + 4; ++jb)
+            gx = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(FB[jb * 64 + lane], rp[jb], gx, 0, 0, 0);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+      if constexpr (CS > 1) {
+        // sum the slices' partial products in slice order (the same order in
+        // every wave of the group, so all of them hold the same y and g)
+        if (descend) redY[wid][lane] = acc;
+        if (needg) redG[wid][lane] = gx;
+        __syncthreads();
+        if (descend) {
+          acc = redY[gw0][lane];
+#pragma unroll
+          for (int c = 1; c < CS; ++c) acc += redY[gw0 + c][lane];
+        }
+        if (needg) {
+          gx = redG[gw0][lane];
+#pragma unroll
+          for (int c = 1; c < CS; ++c) gx += redG[gw0 + c][lane];
+        }
+      }
+      if (descend) {
         shortx4 sg;
 #pragma unroll
         for (int r = 0; r < 4; ++r) sg[r] = sign_bf16(acc[r]);
 #pragma unroll
-        for (int jg = 0; jg < DBP; jg += 4) {
+        for (int jg = 0; jg < DBPW; jg += 4) {
 #pragma unroll
           for (int jb = jg; jb < jg + 4; ++jb)
             G[jb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(BT[jb * 64 + lane], sg, G[jb], 0, 0, 0);
@@ -257,14 +346,6 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(BigArgs g, unsig
         }
       }
       if (needg) {
-        floatx4 gx = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int jg = 0; jg < DBP; jg += 4) {
-#pragma unroll
-          for (int jb = jg; jb < jg + 4; ++jb)
-            gx = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(FB[jb * 64 + lane], rp[jb], gx, 0, 0, 0);
-          __builtin_amdgcn_sched_barrier(0);
-        }
         uint32_t wd = 0;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -274,7 +355,7 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(BigArgs g, unsig
           nonzero |= gv != 0;
           wd |= ((uint32_t)(uint8_t)(int8_t)gv) << (8 * r);
         }
-        if (svalid) srow[4 * ib + q] = wd;
+        if (svalid && lead) srow[4 * ib + q] = wd;
       }
       __syncthreads();
       if (more) {
@@ -291,8 +372,8 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(BigArgs g, unsig
       const bool em = changed && alive;
       if (em && !inrange) alive = false;
       const bool emit = em && inrange;
-      const bool put = emit && inbox && nonzero;
-      n_emit += (q == 0 && emit) ? 1 : 0;
+      const bool put = lead && emit && inbox && nonzero;
+      n_emit += (lead && q == 0 && emit) ? 1 : 0;
       n_inbox += (q == 0 && put) ? 1 : 0;
       const uint64_t pm = __ballot(put && q == 0);
       if (pm != 0) {
@@ -326,23 +407,11 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(BigArgs g, unsig
         }
       }
     }
-    if (!alive && svalid && q == 0 && descend && k > 0) ++n_range;
+    if (!alive && svalid && lead && q == 0 && descend && k > 0) ++n_range;
     if (!descend) break;
 
     __builtin_amdgcn_sched_barrier(0);
     // barrier term, Adam, and the change flag of the new iterate
-    float mu = 0.f;
-#pragma unroll
-    for (int jb = 0; jb < DBP; ++jb)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) mu = fmaxf(mu, fabsf(z[jb][r]));
-    mu = xmax4(mu);
-    float cnt = 0.f;
-#pragma unroll
-    for (int jb = 0; jb < DBP; ++jb)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) cnt += fabsf(z[jb][r]) == mu ? 1.f : 0.f;
-    cnt = xsum4(cnt);
     const bool bar = mu > 0.f && mu < 1.f;
     const float wbar = bar ? lam2 / ((mu * mu) * cnt) : 0.f;
     const double bc1 = a.bc[2 * k], bc2 = a.bc[2 * k + 1];
@@ -358,7 +427,7 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(BigArgs g, unsig
     // next group's loads are issued before the current group is computed
     // (two register stages), and scheduling barriers keep the compiler from
     // hoisting every load of the iteration at once.
-    constexpr int NG = DBP / 4;
+    constexpr int NG = DBPW / 4;
     float mv[2][4][4][2];
 #pragma unroll
     for (int jb = 0; jb < 4; ++jb)
@@ -404,7 +473,7 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(BigArgs g, unsig
     changed = xor4(ch);
   }
 #pragma unroll
-  for (int jb = 0; jb < DBP; ++jb)
+  for (int jb = 0; jb < DBPW; ++jb)
 #pragma unroll
     for (int r = 0; r < 4; ++r) Z[base + (4 * jb + r) * 64] = z[jb][r];
   if (lleft > 0) zero_rows_big(log, lbase + lused, (uint32_t)lleft, lane);
@@ -420,59 +489,67 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(BigArgs g, unsig
   }
 }
 
-template <int DBP, bool BF16F>
+template <int CS, int DBPW, bool BF16F>
 hipError_t launch_big_t(hipStream_t s, const BigArgs& g, unsigned long long* counters) {
-  const int64_t nw = big_waves(g.a.N);
-  const size_t shmem = (size_t)2 * DBP * 64 * 32 + (size_t)16 * g.NB * sizeof(int);
-  auto kern = k_descent_big<DBP, BF16F>;
+  const int64_t groups = (g.a.N + 15) / 16;
+  const int64_t per_block = kWaves / CS;
+  const int64_t blocks = (groups + per_block - 1) / per_block;
+  const size_t shmem = (size_t)2 * CS * DBPW * 64 * 16 + (size_t)16 * g.NB * sizeof(int);
+  auto kern = k_descent_big<CS, DBPW, BF16F>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3((unsigned)(nw / kWaves)), dim3(64 * kWaves), shmem, s, g, counters);
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * kWaves), shmem, s, g, counters);
   return hipGetLastError();
+}
+
+template <bool BF16F>
+hipError_t launch_big_shape(hipStream_t s, const BigArgs& g, BigShape sh, unsigned long long* counters) {
+  switch (sh.cs * 100 + sh.dbpw) {
+    case 108: return launch_big_t<1, 8, BF16F>(s, g, counters);
+    case 112: return launch_big_t<1, 12, BF16F>(s, g, counters);
+    case 116: return launch_big_t<1, 16, BF16F>(s, g, counters);
+    case 212: return launch_big_t<2, 12, BF16F>(s, g, counters);
+    case 216: return launch_big_t<2, 16, BF16F>(s, g, counters);
+    case 412: return launch_big_t<4, 12, BF16F>(s, g, counters);
+    case 416: return launch_big_t<4, 16, BF16F>(s, g, counters);
+  }
+  return hipErrorInvalidValue;
 }
 
 }  // namespace
 
-bool descent_big_supported(int n, int d) { return n <= 1024 && d <= n && big_db(d) > 0; }
-bool descent_big_bf16_supported(int d) { return big_db(d) > 0; }
-int descent_big_dbp(int d) { return big_db(d); }
-size_t big_image_bytes(int n, int d) { return (size_t)blk16(n) * big_db(d) * 64 * 32; }
-size_t big_state_floats(int d, int64_t N) { return 3 * (size_t)big_waves(N) * 4 * big_db(d) * 64; }
+bool descent_big_supported(int n, int d) { return n <= 1024 && d <= n && big_shape(d).cs > 0; }
+bool descent_big_bf16_supported(int d) { return big_shape(d).cs > 0; }
+int descent_big_dbp(int d) {
+  BigShape sh = big_shape(d);
+  return sh.cs * sh.dbpw;
+}
+size_t big_image_bytes(int n, int d) { return (size_t)blk16(n) * descent_big_dbp(d) * 64 * 16; }
+size_t big_state_floats(int d, int64_t N) { return 3 * (size_t)big_waves(N) * 4 * descent_big_dbp(d) * 64; }
 
 hipError_t launch_big_pack(hipStream_t s, int n, int d, const int64_t* B, unsigned char* img) {
-  int NB = blk16(n), DBP = big_db(d);
-  int total = NB * DBP * 64;
-  hipLaunchKernelGGL(k_pack_big, dim3((total + 255) / 256), dim3(256), 0, s, n, d, NB, DBP, B, img);
+  int NB = blk16(n), DBT = descent_big_dbp(d);
+  int total = NB * DBT * 64;
+  hipLaunchKernelGGL(k_pack_big, dim3((total + 255) / 256), dim3(256), 0, s, n, d, NB, DBT, B, img);
   return hipGetLastError();
 }
 
 hipError_t launch_descent_big(hipStream_t s, const DescentArgs& a, const unsigned char* img, float* state,
                               int8_t* scratch, unsigned long long* counters) {
+  const BigShape sh = big_shape(a.d);
+  if (sh.cs == 0) return hipErrorInvalidValue;
   BigArgs g{};
   g.a = a;
   g.NB = blk16(a.n);
   g.img = img;
   g.z = state;
-  const int DBP = big_db(a.d);
-  g.per = big_waves(a.N) * 4 * DBP * 64;
+  // the state layout is that of DBT = cs * dbpw column blocks per start group
+  g.per = big_waves(a.N) * 4 * (sh.cs * sh.dbpw) * 64;
   g.scratch = scratch;
   g.stride = key_stride(a.n);
   // the whole launch uses one forward form: bf16 when a.bf16_iters covers it
   const bool bf = a.bf16_iters >= a.T && a.T > 0;
-  if (bf) {
-    switch (DBP) {
-      case 8: return launch_big_t<8, true>(s, g, counters);
-      case 12: return launch_big_t<12, true>(s, g, counters);
-      case 16: return launch_big_t<16, true>(s, g, counters);
-    }
-    return hipErrorInvalidValue;
-  }
-  switch (DBP) {
-    case 8: return launch_big_t<8, false>(s, g, counters);
-    case 12: return launch_big_t<12, false>(s, g, counters);
-    case 16: return launch_big_t<16, false>(s, g, counters);
-  }
-  return hipErrorInvalidValue;
+  return bf ? launch_big_shape<true>(s, g, sh, counters) : launch_big_shape<false>(s, g, sh, counters);
 }
 
 }  // namespace graver

@@ -12,11 +12,12 @@
 struct graver_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
-  static constexpr int kSlots = 56;
+  static constexpr int kSlots = 64;
   void* buf[kSlots] = {};
   size_t cap[kSlots] = {};
   void* host_pinned = nullptr;  // small pinned staging area
   size_t host_pinned_cap = 0;
+  void* solve_cache = nullptr;  // graver::SolveCache (bases and filtered sets by (A, u - l))
 };
 
 namespace graver {
@@ -34,6 +35,7 @@ enum Slot : int {
   WS_MF_B, WS_MF_BT, WS_MF_STATE, WS_MISC,
   WS_F_CODE, WS_F_HIST, WS_F_OFF, WS_F_CUR, WS_F_BL, WS_A_QFLAG, WS_LOG, WS_LOG_COUNT, WS_MF_BAK, WS_MISC2,
   WS_I_X, WS_I_M, WS_I_V, WS_I_R, WS_I_G,
+  WS_S_KEYS, WS_S_F, WS_S_SOL, WS_S_FEAS, WS_S_IDX, WS_S_STARTS, WS_S_X, WS_S_FV, WS_S_STEPS, WS_S_B, WS_S_P,
   WS_END
 };
 static_assert(WS_END <= graver_ctx::kSlots, "too many workspace slots");
@@ -90,6 +92,10 @@ struct InitArgs {
   double lr, beta1, beta2, eps, lambda3, one_minus_b1, one_minus_b2;
   const double* bc;
 };
+hipError_t launch_gather_rows_i64(hipStream_t s, const int64_t* src, int n, const int32_t* idx, int64_t cnt,
+                                  int64_t* dst);
+void solve_cache_free(graver_ctx* ctx);
+
 hipError_t launch_init_sol(hipStream_t s, const InitArgs& a, const double* x0, uint64_t seed, int64_t first,
                            double* X, double* M, double* V, double* R, double* gscratch, int64_t* xr,
                            int32_t* feas, unsigned int* nfeas);

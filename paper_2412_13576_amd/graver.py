@@ -19,12 +19,14 @@ LIB_PATH = os.path.join(HERE, "libgraver.so")
 
 GRAVER_FP64, GRAVER_FP32, GRAVER_BF16 = 0, 1, 2
 GRAVER_F_QUADRATIC, GRAVER_F_SEPARABLE_POLY = 1, 2
+(GRAVER_OK, GRAVER_E_INVALID, GRAVER_E_INFEASIBLE_START, GRAVER_E_NOT_KERNEL, GRAVER_E_OVERFLOW,
+ GRAVER_E_POOL_FULL, GRAVER_E_NOMEM, GRAVER_E_DEVICE, GRAVER_E_CAPACITY) = range(0, -9, -1)
 STATUS = {0: "OK", -1: "E_INVALID", -2: "E_INFEASIBLE_START", -3: "E_NOT_KERNEL",
           -4: "E_OVERFLOW", -5: "E_POOL_FULL", -6: "E_NOMEM", -7: "E_DEVICE", -8: "E_CAPACITY"}
 
 EXPORTED = ["graver_ctx_create", "graver_ctx_destroy", "graver_ctx_set_stream", "graver_last_error",
             "graver_status_string", "graver_kernel_basis", "graver_extract", "graver_filter",
-            "graver_augment", "graver_init_solutions"]
+            "graver_augment", "graver_init_solutions", "graver_solve"]
 
 
 class GraverError(RuntimeError):
@@ -77,6 +79,21 @@ class InitParams(C.Structure):
                 ("lambda3", C.c_double), ("seed", C.c_uint64), ("first_start", C.c_int64)]
 
 
+class SolveParams(C.Structure):
+    _fields_ = [("extract", ExtractParams), ("init", InitParams), ("max_steps", C.c_int64),
+                ("lll", C.c_int32), ("x_starts", C.c_void_p), ("n_x_starts", C.c_int32), ("reuse", C.c_int32)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("d", C.c_int32), ("reused", C.c_int32), ("best_start", C.c_int32),
+                ("unique", C.c_int64), ("filtered", C.c_int64), ("feasible_starts", C.c_int64),
+                ("augment_steps", C.c_int64), ("ms_basis", C.c_double), ("ms_extract", C.c_double),
+                ("ms_filter", C.c_double), ("ms_init", C.c_double), ("ms_augment", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -108,8 +125,11 @@ def lib():
         L.graver_init_solutions.argtypes = [C.c_void_p, C.POINTER(Problem), C.POINTER(InitParams),
                                             C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                             C.POINTER(C.c_int64)]
+        L.graver_solve.argtypes = [C.c_void_p, C.POINTER(Problem), C.POINTER(ObjectiveC), C.POINTER(SolveParams),
+                                   C.c_void_p, C.POINTER(C.c_double), C.POINTER(SolveStats)]
         for name in ("graver_ctx_create", "graver_ctx_set_stream", "graver_kernel_basis",
-                     "graver_extract", "graver_filter", "graver_augment", "graver_init_solutions"):
+                     "graver_extract", "graver_filter", "graver_augment", "graver_init_solutions",
+                     "graver_solve"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -279,3 +299,28 @@ def init_solutions(ctx: Context, prob: DeviceProblem, params: InitParams, x0=Non
     _check(lib().graver_init_solutions(ctx.h, C.byref(pc), C.byref(params), _ptr(x0), x_out.data_ptr(),
                                        sol.data_ptr(), feas.data_ptr(), C.byref(cnt)))
     return x_out, sol, feas, cnt.value
+
+
+def solve_params(extract: ExtractParams, init: InitParams, max_steps=10 ** 6, lll=True, reuse=True,
+                 x_starts=None) -> SolveParams:
+    """x_starts: optional int64 device tensor (S' x n) of feasible points;
+    the caller keeps it alive for the solve call."""
+    xs = None if x_starts is None else x_starts.contiguous()
+    p = SolveParams(extract, init, max_steps, int(lll), _ptr(xs), 0 if xs is None else xs.shape[0], int(reuse))
+    p._keep = xs
+    return p
+
+
+def solve(ctx: Context, prob: DeviceProblem, obj, params: SolveParams):
+    """graver_solve.  prob.B / prob.P may be None (the library computes
+    them).  Returns (x_best int64 device tensor, f_best, stats dict)."""
+    import torch
+    _, oc = obj
+    n = prob.A.shape[1]
+    x = torch.empty(n, dtype=torch.int64, device=prob.A.device)
+    fb = C.c_double(0.0)
+    stt = SolveStats()
+    pc = prob.c()
+    _check(lib().graver_solve(ctx.h, C.byref(pc), C.byref(oc), C.byref(params), x.data_ptr(), C.byref(fb),
+                              C.byref(stt)))
+    return x, fb.value, stt.as_dict()
