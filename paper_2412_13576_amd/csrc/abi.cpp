@@ -202,12 +202,25 @@ graver_status graver_extract(graver_ctx* ctx, const graver_problem* prob,
   if (prm->collect && (keys_cap < 0 || (keys_cap > 0 && !keys_out)))
     return set_error(GRAVER_E_INVALID, "bad output buffer");
 
-  // B must be a kernel basis: A B = 0 exactly.
-  int a_small = 1;
+  // B must be a kernel basis: A B = 0 exactly.  A's nonzeros (CSR) serve
+  // the exact check of the collected candidates.
+  std::vector<int32_t> csr_rp((size_t)m + 1, 0), csr_col;
+  std::vector<int64_t> csr_val;
   {
     std::vector<int64_t> hA, hB;
     if ((st = copy_to_host(ctx, hA, prob->A, (size_t)m * n)) != GRAVER_OK) return st;
-    for (int64_t av : hA) a_small &= (av > -(1 << 23) && av < (1 << 23)) ? 1 : 0;
+    for (int i = 0; i < m; ++i) {
+      for (int j = 0; j < n; ++j) {
+        const int64_t av = hA[(size_t)i * n + j];
+        if (av <= -((int64_t)1 << 31) || av >= ((int64_t)1 << 31))
+          return set_error(GRAVER_E_OVERFLOW, "|A_ij| must be below 2^31");
+        if (av != 0) {
+          csr_col.push_back(j);
+          csr_val.push_back(av);
+        }
+      }
+      csr_rp[i + 1] = (int32_t)csr_col.size();
+    }
     if ((st = copy_to_host(ctx, hB, prob->B, (size_t)n * d)) != GRAVER_OK) return st;
     for (int i = 0; i < m; ++i)
       for (int c = 0; c < d; ++c) {
@@ -406,7 +419,15 @@ graver_status graver_extract(graver_ctx* ctx, const graver_problem* prob,
           chunk = std::max(1, c / 2);
           continue;
         }
-        if (prm->collect) HIP_TRY(launch_log_insert(s, lg, pool), "log insert");
+        if (prm->collect) {
+          HIP_TRY(launch_log_insert(s, lg, pool), "log insert");
+          // stop as soon as the pool cannot hold the distinct candidates
+          uint32_t pf[3] = {0, 0, 0};
+          HIP_TRY(hipMemcpyAsync(pf, pool.count, sizeof(pf), hipMemcpyDeviceToHost, s), "pool flags");
+          HIP_TRY(hipStreamSynchronize(s), "sync");
+          if (pf[1]) return set_error(GRAVER_E_POOL_FULL, "more distinct candidates than pool_capacity");
+          if (pf[2]) return set_error(GRAVER_E_POOL_FULL, "hash probe limit reached");
+        }
         done += c;
       }
       HIP_TRY(launch_state_io_db(s, d, DBlay, N, fstate, z, mm, vv, 0), "state out");
@@ -447,7 +468,17 @@ graver_status graver_extract(graver_ctx* ctx, const graver_problem* prob,
     EventTimer tm(s);
     unsigned int* bad = (unsigned int*)ws_get(ctx, WS_FLAGS, 64, &st);
     if (!bad) return st;
-    HIP_TRY(launch_verify(s, pool, count, m, prob->A, bad, a_small), "verify");
+    const size_t nnz = csr_col.size();
+    const size_t ints = ((size_t)m + 1 + nnz + 1) / 2 * 2;  // int32 part, padded to 8 bytes
+    auto* csr = (int32_t*)ws_get(ctx, WS_V_CSR, ints * 4 + std::max<size_t>(nnz, 1) * 8, &st);
+    if (!csr) return st;
+    HIP_TRY(hipMemcpyAsync(csr, csr_rp.data(), csr_rp.size() * 4, hipMemcpyHostToDevice, s), "csr");
+    if (nnz) {
+      HIP_TRY(hipMemcpyAsync(csr + m + 1, csr_col.data(), nnz * 4, hipMemcpyHostToDevice, s), "csr");
+      HIP_TRY(hipMemcpyAsync(csr + ints, csr_val.data(), nnz * 8, hipMemcpyHostToDevice, s), "csr");
+    }
+    HIP_TRY(launch_verify(s, pool, count, m, csr, csr + m + 1, reinterpret_cast<const int64_t*>(csr + ints), bad),
+            "verify");
     unsigned int hbad = 0;
     HIP_TRY(hipMemcpyAsync(&hbad, bad, sizeof(hbad), hipMemcpyDeviceToHost, s), "verify flag");
     stt.ms_verify = tm.stop_ms();
@@ -594,8 +625,6 @@ graver_status graver_init_solutions(graver_ctx* ctx, const graver_problem* prob,
   if (!M) return st;
   double* V = (double*)ws_get(ctx, WS_I_V, sn * sizeof(double), &st);
   if (!V) return st;
-  double* R = (double*)ws_get(ctx, WS_I_R, (size_t)S * m * sizeof(double), &st);
-  if (!R) return st;
   double* G = prm->init_mode == 0 ? (double*)ws_get(ctx, WS_I_G, sn * sizeof(double), &st) : nullptr;
   if (prm->init_mode == 0 && !G) return st;
   auto* cnt = (unsigned int*)ws_get(ctx, WS_FLAGS, 64, &st);
@@ -618,7 +647,7 @@ graver_status graver_init_solutions(graver_ctx* ctx, const graver_problem* prob,
   a.one_minus_b1 = 1.0 - prm->beta1;
   a.one_minus_b2 = 1.0 - prm->beta2;
   a.bc = dbc;
-  HIP_TRY(launch_init_sol(s, a, prm->init_mode == 1 ? x0 : nullptr, prm->seed, prm->first_start, X, M, V, R, G,
+  HIP_TRY(launch_init_sol(s, a, prm->init_mode == 1 ? x0 : nullptr, prm->seed, prm->first_start, X, M, V, nullptr, G,
                           sol_out, feasible_out, cnt),
           "init_sol kernels");
   if (x_out) HIP_TRY(hipMemcpyAsync(x_out, X, sn * sizeof(double), hipMemcpyDeviceToDevice, s), "copy x_out");

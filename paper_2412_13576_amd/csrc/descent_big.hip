@@ -5,8 +5,8 @@
 // block (column slices of DBPW 16-column blocks each), so the per-wave
 // register state stays bounded as d grows; a block is 4 waves (one per
 // SIMD), i.e. 4 / CS start groups.  The basis is streamed through LDS one
-// 16-row block at a time (double buffered, the next block prefetched into
-// registers while the current one is used).  z and the gradient
+// 16-row block at a time (double buffered: the next block is loaded from
+// HBM/L2 straight into LDS while the current one is used).  z and the gradient
 // accumulators stay in registers; m and v are read and written once per
 // iteration in the wave-native layout.  Per row block ib each wave computes
 //   y_ib   = B_ib z      over its own columns (binary32 MFMA, or the bf16
@@ -46,13 +46,13 @@ struct BigShape {
   int cs, dbpw;
 };
 
+// Smallest split whose waves hold at most 12 column blocks (wider waves
+// exceed the register file); 16 blocks per wave only beyond d = 768.
 BigShape big_shape(int d) {
   const int db = blk16(d);
-  static const int kCs[] = {1, 2, 4};
-  static const int kPerWave[] = {8, 12, 16};
-  for (int cs : kCs)
-    for (int w : kPerWave)
-      if (cs * w >= db) return {cs, w};
+  static const BigShape kShapes[] = {{1, 8}, {1, 12}, {2, 8}, {2, 12}, {4, 8}, {4, 12}, {4, 16}};
+  for (const BigShape& sh : kShapes)
+    if (sh.cs * sh.dbpw >= db) return sh;
   return {0, 0};
 }
 
@@ -115,6 +115,20 @@ __global__ void k_pack_big(int n, int d, int NB, int DBT, const int64_t* B, unsi
   }
 }
 
+// Row-block chunk (kU4 uint4) from HBM straight into LDS: each wave moves
+// its 64-lane runs of 16 bytes with global_load_lds_dwordx4 (no registers
+// held).  The caller waits for vmcnt(0) before the barrier that publishes it.
+template <int kU4>
+__device__ __forceinline__ void dma_chunk(const uint4* src, uint4* dst) {
+  const int wbase = threadIdx.x & ~63;
+#pragma unroll
+  for (int t = 0; t < kU4 / 256; ++t)
+    __builtin_amdgcn_global_load_lds(src + threadIdx.x + t * 256,
+                                     (__attribute__((address_space(3))) void*)(dst + wbase + t * 256), 16, 0, 0);
+}
+
+__device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }  // vmcnt(0)
+
 struct BigArgs {
   DescentArgs a;
   int NB;
@@ -136,7 +150,6 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(BigArgs g, unsig
   const DescentArgs& a = g.a;
   constexpr int DBT = CS * DBPW;                        // column blocks of the image
   constexpr int kChunkU4 = DBT * 64;                    // uint4 per row-block chunk
-  constexpr int kPerThread = kChunkU4 / (64 * kWaves);  // DBT / 4
   extern __shared__ __align__(16) unsigned char smem[];
   uint4* buf0 = reinterpret_cast<uint4*>(smem);
   uint4* buf1 = buf0 + kChunkU4;
@@ -208,6 +221,10 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(BigArgs g, unsig
       }
     cnt = xsum4(cnt);
     inrange = xand4(inrange);
+    // stage row block 0 (every read of the buffers in the previous
+    // iteration ended before its last barrier); the barrier below publishes it
+    dma_chunk<kChunkU4>(img, buf0);
+    wait_vmem();
     if constexpr (CS > 1) {
       if (q == 0) {
         xmu[wid][sl] = mu;
@@ -260,40 +277,36 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(BigArgs g, unsig
     for (int jb = 0; jb < DBPW; ++jb) G[jb] = floatx4{0.f, 0.f, 0.f, 0.f};
     int inbox = 1, nonzero = 0;
 
-    // stage row block 0
-    __syncthreads();
-    for (int t = 0; t < kPerThread; ++t) buf0[threadIdx.x + t * 64 * kWaves] = img[threadIdx.x + t * 64 * kWaves];
-    __syncthreads();
     for (int ib = 0; ib < NB; ++ib) {
       uint4* cur = (ib & 1) ? buf1 : buf0;
       uint4* nxt = (ib & 1) ? buf0 : buf1;
-      uint4 pre[kPerThread];
       const bool more = ib + 1 < NB;
-      if (more) {
-        const uint4* src = img + (size_t)(ib + 1) * kChunkU4;
-        asm volatile("" : "+v"(src));
-#pragma unroll
-        for (int t = 0; t < kPerThread; ++t) pre[t] = src[threadIdx.x + t * 64 * kWaves];
-      }
+      // the other buffer was last read before the previous row block's final
+      // barrier: the next row block streams into it during this one
+      if (more) dma_chunk<kChunkU4>(img + (size_t)(ib + 1) * kChunkU4, nxt);
       const shortx4* FB = reinterpret_cast<const shortx4*>(cur) + jb0 * 64;
       const shortx4* BT = reinterpret_cast<const shortx4*>(cur) + (DBT + jb0) * 64;
       floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
       floatx4 gx = floatx4{0.f, 0.f, 0.f, 0.f};
       if (descend) {
-        // column blocks in groups of 4 with scheduling barriers in between:
-        // bounds the number of LDS operands loaded ahead (register pressure)
+        // column blocks in groups of 4 with scheduling barriers in between
+        // (bounds the number of LDS operands loaded ahead); independent
+        // accumulators shorten the dependent MFMA chains
         if constexpr (BF16F) {
+          floatx4 a1 = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
           for (int jg = 0; jg < DBPW; jg += 4) {
 #pragma unroll
             for (int jb = jg; jb < jg + 4; ++jb) {
               const shortx4 A = FB[jb * 64 + lane];
               acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, hi[jb], acc, 0, 0, 0);
-              acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, lo[jb], acc, 0, 0, 0);
+              a1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, lo[jb], a1, 0, 0, 0);
             }
             __builtin_amdgcn_sched_barrier(0);
           }
+          acc += a1;
         } else {
+          floatx4 a4[4] = {acc, acc, acc, acc};
 #pragma unroll
           for (int jg = 0; jg < DBPW; jg += 4) {
 #pragma unroll
@@ -301,10 +314,11 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(BigArgs g, unsig
               const shortx4 A = FB[jb * 64 + lane];
 #pragma unroll
               for (int r = 0; r < 4; ++r)
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(bf16_to_f(A[r]), z[jb][r], acc, 0, 0, 0);
+                a4[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(bf16_to_f(A[r]), z[jb][r], a4[r], 0, 0, 0);
             }
             __builtin_amdgcn_sched_barrier(0);
           }
+          acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
         }
       }
       if (needg) {
@@ -318,7 +332,9 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(BigArgs g, unsig
       }
       if constexpr (CS > 1) {
         // sum the slices' partial products in slice order (the same order in
-        // every wave of the group, so all of them hold the same y and g)
+        // every wave of the group, so all of them hold the same y and g); the
+        // next row block goes to the other buffer, whose last reads ended
+        // before the previous row block's final barrier
         if (descend) redY[wid][lane] = acc;
         if (needg) redG[wid][lane] = gx;
         __syncthreads();
@@ -357,11 +373,9 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(BigArgs g, unsig
         }
         if (svalid && lead) srow[4 * ib + q] = wd;
       }
-      __syncthreads();
-      if (more) {
-#pragma unroll
-        for (int t = 0; t < kPerThread; ++t) nxt[threadIdx.x + t * 64 * kWaves] = pre[t];
-      }
+      // publishes the next row block, and (CS > 1) ends the reads of the
+      // partial sums before they are rewritten
+      wait_vmem();
       __syncthreads();
     }
 
@@ -507,9 +521,9 @@ hipError_t launch_big_shape(hipStream_t s, const BigArgs& g, BigShape sh, unsign
   switch (sh.cs * 100 + sh.dbpw) {
     case 108: return launch_big_t<1, 8, BF16F>(s, g, counters);
     case 112: return launch_big_t<1, 12, BF16F>(s, g, counters);
-    case 116: return launch_big_t<1, 16, BF16F>(s, g, counters);
+    case 208: return launch_big_t<2, 8, BF16F>(s, g, counters);
     case 212: return launch_big_t<2, 12, BF16F>(s, g, counters);
-    case 216: return launch_big_t<2, 16, BF16F>(s, g, counters);
+    case 408: return launch_big_t<4, 8, BF16F>(s, g, counters);
     case 412: return launch_big_t<4, 12, BF16F>(s, g, counters);
     case 416: return launch_big_t<4, 16, BF16F>(s, g, counters);
   }

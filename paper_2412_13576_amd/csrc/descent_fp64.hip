@@ -61,6 +61,10 @@ __global__ void k_box_points(int n, int64_t N, const int64_t* l, const int64_t* 
   }
 }
 
+__global__ void k_zero_nfeas(unsigned int* p) {
+  if (threadIdx.x == 0) *p = 0u;
+}
+
 // X[s, j] = G[j * N + s] (j-major to row-major).
 __global__ void k_transpose_f64(int n, int64_t N, const double* G, double* X) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -194,32 +198,41 @@ hipError_t launch_descent_fp64(hipStream_t s, const DescentArgs& a, double* z, d
 }
 
 // ---- initial feasible solutions (eq. init_sol) ---------------------------
-// One thread per start, binary64 with the oracle's operation order:
-//   res_i = (sum_j A_ij x_j) - b_i,  grad_j = 2 (sum_i A_ij res_i)
-//           + lam3 ((ceil x_j + floor x_j) - 2 x_j),
-// Adam, then projection onto [l, u]; finally r = round(x) and the exact
-// test A r = b, l <= r <= u.  X, M, V are row-major S x n, R is S x m.
+// One block per start, binary64 with the oracle's operation order.  Each
+// iteration: thread i forms res_i = (sum_j A_ij x_j) - b_i (j ascending from
+// 0.0); after a barrier thread j forms grad_j = 2 (sum_i A_ij res_i)
+// + lam3 ((ceil x_j + floor x_j) - 2 x_j) (i ascending), takes the Adam step
+// and projects onto [l, u].  x and res live in LDS; m and v (row-major
+// S x n) stay in HBM, one coalesced read and write per iteration.  Finally
+// r = round(x) and the exact test A r = b, l <= r <= u.
 __global__ void k_init_sol(InitArgs a, double* __restrict__ X, double* __restrict__ M, double* __restrict__ V,
-                           double* __restrict__ R, int64_t* __restrict__ xr, int32_t* __restrict__ feas,
-                           unsigned int* nfeas) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= a.S) return;
+                           int64_t* __restrict__ xr, int32_t* __restrict__ feas, unsigned int* nfeas) {
+  extern __shared__ double ish[];
   const int n = a.n, m = a.m;
+  const int64_t s = blockIdx.x;
+  double* xs = ish;       // n
+  double* rs = ish + n;   // m
   double* x = X + (size_t)s * n;
   double* mm = M + (size_t)s * n;
   double* vv = V + (size_t)s * n;
-  double* res = R + (size_t)s * m;
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    xs[j] = x[j];
+    mm[j] = 0.0;
+    vv[j] = 0.0;
+  }
+  __syncthreads();
   for (int k = 0; k < a.T; ++k) {
-    for (int i = 0; i < m; ++i) {
+    for (int i = threadIdx.x; i < m; i += blockDim.x) {
       double acc = 0.0;
-      for (int j = 0; j < n; ++j) acc = acc + (double)a.A[(size_t)i * n + j] * x[j];
-      res[i] = acc - (double)a.b[i];
+      for (int j = 0; j < n; ++j) acc = acc + (double)a.A[(size_t)i * n + j] * xs[j];
+      rs[i] = acc - (double)a.b[i];
     }
+    __syncthreads();
     const double bc1 = a.bc[2 * k], bc2 = a.bc[2 * k + 1];
-    for (int j = 0; j < n; ++j) {
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
       double g = 0.0;
-      for (int i = 0; i < m; ++i) g = g + (double)a.A[(size_t)i * n + j] * res[i];
-      const double xj = x[j];
+      for (int i = 0; i < m; ++i) g = g + (double)a.A[(size_t)i * n + j] * rs[i];
+      const double xj = xs[j];
       double t = ceil(xj) + floor(xj);
       t = t - 2.0 * xj;
       const double grad = 2.0 * g + a.lambda3 * t;
@@ -230,30 +243,37 @@ __global__ void k_init_sol(InitArgs a, double* __restrict__ X, double* __restric
       const double mhat = mj / bc1;
       const double vhat = vj / bc2;
       double xn = xj - (a.lr * mhat) / (sqrt(vhat) + a.eps);
-      xn = fmin(fmax(xn, (double)a.l[j]), (double)a.u[j]);
-      x[j] = xn;
+      xs[j] = fmin(fmax(xn, (double)a.l[j]), (double)a.u[j]);
     }
+    __syncthreads();
   }
-  bool ok = true;
   int64_t* r = xr + (size_t)s * n;
-  for (int j = 0; j < n; ++j) {
-    const int64_t v = (int64_t)rint(x[j]);
-    r[j] = v;
-    ok = ok && v >= a.l[j] && v <= a.u[j];
+  int ok = 1;
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    const double xj = xs[j];
+    x[j] = xj;
+    const double rj = rint(xj);  // |rj| < 2^53 (bounds checked by the host)
+    r[j] = (int64_t)rj;
+    xs[j] = rj;
+    ok &= (rj >= (double)a.l[j] && rj <= (double)a.u[j]) ? 1 : 0;
   }
-  for (int i = 0; i < m && ok; ++i) {
+  __syncthreads();
+  for (int i = threadIdx.x; i < m; i += blockDim.x) {
     int64_t acc = 0;
-    for (int j = 0; j < n; ++j) acc += a.A[(size_t)i * n + j] * r[j];
-    ok = acc == a.b[i];
+    for (int j = 0; j < n; ++j) acc += a.A[(size_t)i * n + j] * (int64_t)xs[j];
+    ok &= acc == a.b[i] ? 1 : 0;
   }
-  feas[s] = ok ? 1 : 0;
-  if (ok) atomicAdd(nfeas, 1u);
+  ok = __syncthreads_and(ok);
+  if (threadIdx.x == 0) {
+    feas[s] = ok;
+    if (ok) atomicAdd(nfeas, 1u);
+  }
 }
 
 hipError_t launch_init_sol(hipStream_t s, const InitArgs& a, const double* x0, uint64_t seed, int64_t first,
                            double* X, double* M, double* V, double* R, double* gscratch, int64_t* xr,
                            int32_t* feas, unsigned int* nfeas) {
-  const unsigned blocks = (unsigned)((a.S + 63) / 64);
+  (void)R;
   if (x0) {
     hipMemcpyAsync(X, x0, (size_t)a.S * a.n * sizeof(double), hipMemcpyDeviceToDevice, s);
   } else {
@@ -262,10 +282,9 @@ hipError_t launch_init_sol(hipStream_t s, const InitArgs& a, const double* x0, u
     hipLaunchKernelGGL(k_transpose_f64, dim3((unsigned)((a.S * a.n + 255) / 256)), dim3(256), 0, s, a.n, a.S,
                        gscratch, X);
   }
-  hipMemsetAsync(M, 0, (size_t)a.S * a.n * sizeof(double), s);
-  hipMemsetAsync(V, 0, (size_t)a.S * a.n * sizeof(double), s);
-  hipMemsetAsync(nfeas, 0, sizeof(unsigned int), s);
-  hipLaunchKernelGGL(k_init_sol, dim3(blocks), dim3(64), 0, s, a, X, M, V, R, xr, feas, nfeas);
+  hipLaunchKernelGGL(k_zero_nfeas, dim3(1), dim3(64), 0, s, nfeas);
+  const size_t shmem = (size_t)(a.n + a.m) * sizeof(double);
+  hipLaunchKernelGGL(k_init_sol, dim3((unsigned)a.S), dim3(128), shmem, s, a, X, M, V, xr, feas, nfeas);
   return hipGetLastError();
 }
 

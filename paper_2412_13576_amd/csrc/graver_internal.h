@@ -36,6 +36,7 @@ enum Slot : int {
   WS_F_CODE, WS_F_HIST, WS_F_OFF, WS_F_CUR, WS_F_BL, WS_A_QFLAG, WS_LOG, WS_LOG_COUNT, WS_MF_BAK, WS_MISC2,
   WS_I_X, WS_I_M, WS_I_V, WS_I_R, WS_I_G,
   WS_S_KEYS, WS_S_F, WS_S_SOL, WS_S_FEAS, WS_S_IDX, WS_S_STARTS, WS_S_X, WS_S_FV, WS_S_STEPS, WS_S_B, WS_S_P,
+  WS_V_CSR,
   WS_END
 };
 static_assert(WS_END <= graver_ctx::kSlots, "too many workspace slots");
@@ -131,8 +132,8 @@ hipError_t launch_descent_big(hipStream_t s, const DescentArgs& a, const unsigne
 
 hipError_t launch_pool_clear(hipStream_t s, PoolDev p);
 hipError_t launch_log_insert(hipStream_t s, LogDev log, PoolDev pool);
-hipError_t launch_verify(hipStream_t s, PoolDev p, uint32_t count, int m, const int64_t* A,
-                         unsigned int* bad, int a_small);
+hipError_t launch_verify(hipStream_t s, PoolDev p, uint32_t count, int m, const int32_t* rp, const int32_t* col,
+                         const int64_t* val, unsigned int* bad);
 hipError_t launch_sort_keys(hipStream_t s, const int8_t* keys, int stride, int n, uint32_t count,
                             uint32_t* idx, uint32_t* tmp, int by_l1, const int32_t* l1);
 hipError_t launch_gather_keys(hipStream_t s, const int8_t* keys, int stride, int n,

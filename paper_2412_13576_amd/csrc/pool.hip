@@ -2,6 +2,8 @@
 // A g = 0 (condition C1), lexicographic sorting and gathering of int8 keys.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "graver_internal.h"
 #include "pool_device.h"
 
@@ -44,49 +46,47 @@ hipError_t launch_log_insert(hipStream_t s, LogDev log, PoolDev pool) {
   return hipGetLastError();
 }
 
-// One thread per key: every row of A must annihilate the key exactly
-// (condition C1).  A is staged in LDS as int32 when every |A_ij| < 2^23, so
-// each row sum is below 2^23 * 127 * n < 2^63 in int64 accumulation; the key
-// is read four bytes at a time.
-__global__ void k_verify(const int8_t* keys, int stride, int n, uint32_t count, int m,
-                         const int64_t* __restrict__ A, unsigned int* bad, int use_lds) {
-  extern __shared__ int32_t sA[];
-  if (use_lds) {
-    for (int t = threadIdx.x; t < m * n; t += blockDim.x) sA[t] = (int32_t)A[t];
+// Condition C1, A g = 0 exactly, for every pool key.  A is given as CSR
+// (row_ptr m+1, col and val per nonzero).  A block handles 4 keys per round
+// (one per wave): the key rows are staged in LDS with coalesced loads, then
+// lane r of each wave forms the sums of rows r, r+64, ... over the row's
+// nonzeros in int64 (|A_ij| < 2^31 and |g_j| <= 127 with n <= 4096 keep every
+// partial sum below 2^63).
+__global__ void k_verify(const int8_t* keys, int stride, uint32_t count, int m, const int32_t* __restrict__ rp,
+                         const int32_t* __restrict__ col, const int64_t* __restrict__ val, unsigned int* bad) {
+  extern __shared__ __align__(16) int8_t sk[];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int8_t* key = sk + (size_t)wid * stride;
+  const int words = stride / 4;
+  for (uint32_t base = blockIdx.x * 4u; base < count; base += gridDim.x * 4u) {
+    const uint32_t k = base + (uint32_t)wid;
+    if (k < count) {
+      const uint32_t* src = reinterpret_cast<const uint32_t*>(keys + (size_t)k * stride);
+      for (int w = lane; w < words; w += 64) reinterpret_cast<uint32_t*>(key)[w] = src[w];
+    }
     __syncthreads();
-  }
-  uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= count) return;
-  const uint32_t* g4 = reinterpret_cast<const uint32_t*>(keys + (size_t)k * stride);
-  const int nw = (n + 3) / 4;
-  for (int i = 0; i < m; ++i) {
-    int64_t s = 0;
-    for (int w = 0; w < nw; ++w) {
-      uint32_t word = g4[w];
-      for (int b = 0; b < 4; ++b) {
-        int j = 4 * w + b;
-        if (j >= n) break;
-        int gv = (int8_t)(word >> (8 * b));
-        int64_t av = use_lds ? (int64_t)sA[i * n + j] : A[(size_t)i * n + j];
-        s += av * gv;
+    if (k < count) {
+      int ok = 1;
+      for (int i = lane; i < m; i += 64) {
+        int64_t acc = 0;
+        for (int p = rp[i]; p < rp[i + 1]; ++p) acc += val[p] * (int64_t)key[col[p]];
+        ok &= acc == 0 ? 1 : 0;
       }
+      if (!ok) atomicAdd(bad, 1u);
     }
-    if (s != 0) {
-      atomicAdd(bad, 1u);
-      return;
-    }
+    __syncthreads();
   }
 }
 
-hipError_t launch_verify(hipStream_t s, PoolDev p, uint32_t count, int m, const int64_t* A,
-                         unsigned int* bad, int a_small) {
+hipError_t launch_verify(hipStream_t s, PoolDev p, uint32_t count, int m, const int32_t* rp, const int32_t* col,
+                         const int64_t* val, unsigned int* bad) {
   hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, reinterpret_cast<uint64_t*>(bad),
                      (uint64_t)1, (uint64_t)0);
   if (count == 0) return hipGetLastError();
-  size_t lds = (size_t)m * p.n * sizeof(int32_t);
-  int use_lds = a_small && lds <= 48 * 1024;
-  hipLaunchKernelGGL(k_verify, dim3((count + 255) / 256), dim3(256), use_lds ? lds : 0, s, p.keys, p.stride,
-                     p.n, count, m, A, bad, use_lds);
+  const uint32_t rounds = (count + 3) / 4;
+  const unsigned blocks = (unsigned)std::min<uint32_t>(rounds, 8192u);
+  hipLaunchKernelGGL(k_verify, dim3(blocks), dim3(256), (size_t)4 * p.stride, s, p.keys, p.stride, count, m, rp,
+                     col, val, bad);
   return hipGetLastError();
 }
 
