@@ -231,6 +231,28 @@ graver_status graver_init_solutions(graver_ctx* ctx, const graver_problem* prob,
                                     double* x_out, int64_t* sol_out, int32_t* feasible_out,
                                     int64_t* n_feasible);
 
+/* ---- linear inequalities (Section 3.4) --------------------------------- */
+
+/* Slack form of  A x = b, G x >= h, l <= x <= u  (eq. NLIP_ineq_slack):
+ *     [A 0; G -I] (x, s) = (b, h),  l <= x <= u,  0 <= s <= s_max,
+ * s_max_i = sum_j max(G_ij l_j, G_ij u_j) - h_i (the largest slack any x in
+ * the box has, so no feasible point is lost), and, when B (an n x d kernel
+ * basis of A) is given, the kernel basis [B; G B] of the lifted matrix (the
+ * corollary of Section 3.4): its surrogate is eq. surrogate_ineq.  The
+ * lifted program (n + m' variables, m + m' rows) then goes through the
+ * ordinary entry points; the first n coordinates of its points are x.
+ * All host pointers, row-major.  m may be 0 (no equalities; then B = I).
+ * Outputs: A_out (m+m') x (n+m'), b_out m+m', l_out and u_out n+m',
+ * Bt_out (n+m') x d.  Errors: GRAVER_E_INVALID when some row of G x >= h
+ * holds nowhere in the box; GRAVER_E_OVERFLOW on int64 overflow.  (The
+ * int8 keys of the extraction need every u - l, slack rows included, at
+ * most 127.) */
+graver_status graver_lift_inequalities(int32_t m, int32_t n, const int64_t* A, const int64_t* b,
+                                       const int64_t* l, const int64_t* u, int32_t mi,
+                                       const int64_t* G, const int64_t* h, int32_t d,
+                                       const int64_t* B, int64_t* A_out, int64_t* b_out,
+                                       int64_t* l_out, int64_t* u_out, int64_t* Bt_out);
+
 /* ---- end-to-end solve (MAPE, Section 3.3) ----------------------------- */
 
 typedef struct {

@@ -33,6 +33,7 @@ SOURCES = {
     "filter.hip": [],
     "augment.hip": ["-ffp-contract=off"],
     "solve.cpp": ["-x", "hip"],
+    "inequality.cpp": ["-x", "hip"],
 }
 
 

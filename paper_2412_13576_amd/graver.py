@@ -26,7 +26,7 @@ STATUS = {0: "OK", -1: "E_INVALID", -2: "E_INFEASIBLE_START", -3: "E_NOT_KERNEL"
 
 EXPORTED = ["graver_ctx_create", "graver_ctx_destroy", "graver_ctx_set_stream", "graver_last_error",
             "graver_status_string", "graver_kernel_basis", "graver_extract", "graver_filter",
-            "graver_augment", "graver_init_solutions", "graver_solve"]
+            "graver_augment", "graver_init_solutions", "graver_solve", "graver_lift_inequalities"]
 
 
 class GraverError(RuntimeError):
@@ -127,9 +127,13 @@ def lib():
                                             C.POINTER(C.c_int64)]
         L.graver_solve.argtypes = [C.c_void_p, C.POINTER(Problem), C.POINTER(ObjectiveC), C.POINTER(SolveParams),
                                    C.c_void_p, C.POINTER(C.c_double), C.POINTER(SolveStats)]
+        L.graver_lift_inequalities.argtypes = [C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                               C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
+                                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                               C.c_void_p]
         for name in ("graver_ctx_create", "graver_ctx_set_stream", "graver_kernel_basis",
                      "graver_extract", "graver_filter", "graver_augment", "graver_init_solutions",
-                     "graver_solve"):
+                     "graver_solve", "graver_lift_inequalities"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -324,3 +328,23 @@ def solve(ctx: Context, prob: DeviceProblem, obj, params: SolveParams):
     _check(lib().graver_solve(ctx.h, C.byref(pc), C.byref(oc), C.byref(params), x.data_ptr(), C.byref(fb),
                               C.byref(stt)))
     return x, fb.value, stt.as_dict()
+
+
+def lift_inequalities(A, b, l, u, G, h, B=None):
+    """graver_lift_inequalities on host arrays: (A', b', l', u', [B; G B])."""
+    c = lambda x: np.ascontiguousarray(x, dtype=np.int64)
+    A, b, l, u, G, h = c(A), c(b), c(l), c(u), c(G), c(h)
+    m, n = A.shape
+    mi = G.shape[0]
+    A2 = np.zeros((m + mi, n + mi), np.int64)
+    b2 = np.zeros(m + mi, np.int64)
+    l2 = np.zeros(n + mi, np.int64)
+    u2 = np.zeros(n + mi, np.int64)
+    d = 0 if B is None else B.shape[1]
+    Bt = None if B is None else np.zeros((n + mi, d), np.int64)
+    Bc = None if B is None else c(B)
+    _check(lib().graver_lift_inequalities(m, n, A.ctypes.data if m else None, b.ctypes.data if m else None,
+                                          l.ctypes.data, u.ctypes.data, mi, G.ctypes.data, h.ctypes.data, d,
+                                          None if Bc is None else Bc.ctypes.data, A2.ctypes.data, b2.ctypes.data,
+                                          l2.ctypes.data, u2.ctypes.data, None if Bt is None else Bt.ctypes.data))
+    return A2, b2, l2, u2, Bt

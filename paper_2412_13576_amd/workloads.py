@@ -182,6 +182,22 @@ def identity_block_instance(seed: int, n: int, m: int, density: float = 0.2) -> 
                     meta=dict(law="identity_block", seed=seed))
 
 
+def inequality_rows(inst: Instance, mi: int, seed: int, nnz: int = 4, mag: int = 1):
+    """Inequalities G x >= h that the instance's x0 satisfies: each row of G
+    has `nnz` distinct random columns with entries uniform in
+    {+-1, ..., +-mag}; h = G x0 - t with t uniform in {0, ..., 3}.
+    Returns (G (mi, n) int64, h (mi,) int64)."""
+    rng = _rng(seed)
+    n = inst.n
+    G = np.zeros((mi, n), np.int64)
+    for i in range(mi):
+        cols = rng.choice(n, size=nnz, replace=False)
+        vals = rng.integers(1, mag + 1, size=nnz) * np.where(rng.random(nnz) < 0.5, -1, 1)
+        G[i, cols] = vals
+    h = G @ inst.x0 - rng.integers(0, 4, size=mi)
+    return G, h.astype(np.int64)
+
+
 def random_instance(seed: int, m: int, n: int, lo: int = -3, hi: int = 3,
                     bound: int = 5, density: float = 1.0) -> Instance:
     """Small random instance for tests: A iid uniform integers in [lo, hi]

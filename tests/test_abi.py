@@ -67,3 +67,30 @@ def test_host_kernel_basis_overflow_is_reported():
     A = np.array([[2 ** 50 + 1, 2 ** 50 + 3, 2 ** 49 + 5]], dtype=np.int64)
     B, _ = G.kernel_basis(A, lll=False)
     assert np.array_equal(B, np.array(lattice.hnf_kernel_basis(A)["B"], dtype=np.int64))
+
+
+def test_lift_inequalities_matches_oracle():
+    """The host slack form and lifted basis equal the oracle's, bit for bit."""
+    from oracle import inequality as Q
+    for inst, mi, seed in [(W.tiny_instance(1000), 2, 1), (W.qp_instance(2000), 10, 2), (W.quartic_instance(), 6, 3)]:
+        Gm, h = W.inequality_rows(inst, mi, seed, nnz=4, mag=2)
+        B = lattice.kernel_basis(inst.A) if inst.n <= 100 else None
+        A2, b2, l2, u2, Bt = G.lift_inequalities(inst.A, inst.b, inst.l, inst.u, Gm, h, B)
+        Ao, bo, lo, uo = Q.lift(inst.A, inst.b, inst.l, inst.u, Gm, h)
+        assert np.array_equal(A2, Ao) and np.array_equal(b2, bo)
+        assert np.array_equal(l2, lo) and np.array_equal(u2, uo)
+        if B is not None:
+            assert np.array_equal(Bt, Q.lift_basis(B, Gm))
+            assert np.all(A2 @ Bt == 0)
+        assert np.all(A2 @ Q.lift_point(inst.x0, Gm, h) == b2)
+
+
+def test_lift_inequalities_errors():
+    inst = W.tiny_instance(1000)
+    Gm = np.ones((1, 8), np.int64)
+    with pytest.raises(G.GraverError) as e:
+        G.lift_inequalities(inst.A, inst.b, inst.l, inst.u, Gm, np.array([100]))
+    assert e.value.status == G.GRAVER_E_INVALID
+    with pytest.raises(G.GraverError) as e:
+        G.lift_inequalities(inst.A, inst.b, inst.l, inst.u, Gm * (1 << 60), np.array([0]))
+    assert e.value.status == G.GRAVER_E_OVERFLOW
