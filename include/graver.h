@@ -178,6 +178,40 @@ graver_status graver_extract(graver_ctx* ctx, const graver_problem* prob,
                              int8_t* keys_out, int64_t keys_cap, int64_t* count_out,
                              graver_extract_stats* stats);
 
+/* ---- batched extraction ----------------------------------------------- */
+
+typedef struct {
+  int32_t autotune;  /* 1: the large-basis tile shape of each basis size is the
+                        fastest candidate in a short timed trial (kept in the
+                        context); 0: the fixed shape table                     */
+  int32_t use_graph; /* 1: each round of the batched descent (state backups,
+                        grids, log inserts) is captured and run as a HIP graph */
+} graver_batch_params;
+
+typedef struct {
+  double ms_descent; /* device time of the batched descent rounds             */
+  int32_t launches;  /* descent grids launched                                */
+  int32_t replays;   /* instances replayed alone after a log overflow         */
+  int32_t graphs;    /* rounds run as a graph                                 */
+} graver_batch_stats;
+
+/* Parallel Extraction for `count` independent instances in one call.
+ * Instance i is described by probs[i], params[i], states[i] (states may be
+ * NULL, entries may be NULL) and writes keys_out[i] (device, keys_cap[i]
+ * rows), count_out[i] and stats[i] (may be NULL), exactly as graver_extract
+ * does for one instance.  Every instance with n > 128 or d > 128 in FP32 or
+ * BF16 runs in a shared grid with the other instances of the same tile
+ * shape and forward form (one launch for all of them; the bf16 phase and the
+ * FP32 polish of BF16 instances are two rounds); the other instances run
+ * alone.  With the fixed shape table an instance's results equal a single
+ * graver_extract call's bit for bit.  Each instance keeps its own device
+ * workspace in the context.  The first error ends the call. */
+graver_status graver_extract_batch(graver_ctx* ctx, int32_t count, const graver_problem* probs,
+                                   const graver_extract_params* params, graver_state* const* states,
+                                   int8_t* const* keys_out, const int64_t* keys_cap, int64_t* count_out,
+                                   graver_extract_stats* stats, const graver_batch_params* batch,
+                                   graver_batch_stats* batch_stats);
+
 /* Minimality filter with deduplication (condition C3, Section 3; the
  * conformal order of Section 1).  Input: count_in int8 rows of n bytes
  * (device).  The set C = X u (-X) without 0 is formed; g in C is dropped

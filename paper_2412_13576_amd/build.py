@@ -32,6 +32,7 @@ SOURCES = {
     "descent_big.hip": ["-ffp-contract=fast"],
     "filter.hip": [],
     "augment.hip": ["-ffp-contract=off"],
+    "extract.cpp": ["-x", "hip"],
     "solve.cpp": ["-x", "hip"],
     "inequality.cpp": ["-x", "hip"],
 }

@@ -27,14 +27,14 @@ graver_status hip_error(hipError_t e, const char* what) {
   return set_error(GRAVER_E_DEVICE, msg);
 }
 
-void* ws_get(graver_ctx* ctx, int slot, size_t bytes, graver_status* st) {
+void* ws_get(graver_ctx* ctx, Ws& w, int slot, size_t bytes, graver_status* st) {
   if (bytes == 0) bytes = 256;
-  if (ctx->cap[slot] >= bytes) return ctx->buf[slot];
-  if (ctx->buf[slot]) {
+  if (w.cap[slot] >= bytes) return w.buf[slot];
+  if (w.buf[slot]) {
     hipStreamSynchronize(ctx->stream);
-    hipFree(ctx->buf[slot]);
-    ctx->buf[slot] = nullptr;
-    ctx->cap[slot] = 0;
+    hipFree(w.buf[slot]);
+    w.buf[slot] = nullptr;
+    w.cap[slot] = 0;
   }
   size_t want = bytes + bytes / 4;
   void* p = nullptr;
@@ -44,49 +44,23 @@ void* ws_get(graver_ctx* ctx, int slot, size_t bytes, graver_status* st) {
     *st = set_error(GRAVER_E_NOMEM, "device workspace allocation failed");
     return nullptr;
   }
-  ctx->buf[slot] = p;
-  ctx->cap[slot] = want;
+  w.buf[slot] = p;
+  w.cap[slot] = want;
   return p;
 }
 
-namespace {
-
-#define HIP_TRY(expr, what)                 \
-  do {                                      \
-    hipError_t e_ = (expr);                 \
-    if (e_ != hipSuccess) return hip_error(e_, what); \
-  } while (0)
-
-template <class T>
-graver_status copy_to_host(graver_ctx* ctx, std::vector<T>& dst, const T* src, size_t count) {
-  dst.resize(count);
-  if (count == 0) return GRAVER_OK;
-  HIP_TRY(hipMemcpyAsync(dst.data(), src, count * sizeof(T), hipMemcpyDeviceToHost, ctx->stream),
-          "device to host copy");
-  HIP_TRY(hipStreamSynchronize(ctx->stream), "stream synchronize");
-  return GRAVER_OK;
+void* ws_get(graver_ctx* ctx, int slot, size_t bytes, graver_status* st) {
+  return ws_get(ctx, ctx->ws, slot, bytes, st);
 }
 
-struct EventTimer {
-  hipEvent_t a = nullptr, b = nullptr;
-  hipStream_t s;
-  explicit EventTimer(hipStream_t st) : s(st) {
-    hipEventCreate(&a);
-    hipEventCreate(&b);
-    hipEventRecord(a, s);
-  }
-  double stop_ms() {
-    float ms = 0.f;
-    hipEventRecord(b, s);
-    hipEventSynchronize(b);
-    hipEventElapsedTime(&ms, a, b);
-    return ms;
-  }
-  ~EventTimer() {
-    hipEventDestroy(a);
-    hipEventDestroy(b);
-  }
-};
+void ws_free(Ws& w) {
+  for (int i = 0; i < Ws::kSlots; ++i)
+    if (w.buf[i]) {
+      hipFree(w.buf[i]);
+      w.buf[i] = nullptr;
+      w.cap[i] = 0;
+    }
+}
 
 graver_status validate_problem(graver_ctx* ctx, const graver_problem* p, bool need_b,
                                std::vector<int64_t>& hl, std::vector<int64_t>& hu) {
@@ -106,7 +80,6 @@ graver_status validate_problem(graver_ctx* ctx, const graver_problem* p, bool ne
   return GRAVER_OK;
 }
 
-}  // namespace
 }  // namespace graver
 
 using namespace graver;
@@ -155,9 +128,14 @@ void graver_ctx_destroy(graver_ctx* ctx) {
   if (!ctx) return;
   hipSetDevice(ctx->device);
   hipStreamSynchronize(ctx->stream);
-  for (int i = 0; i < graver_ctx::kSlots; ++i)
-    if (ctx->buf[i]) hipFree(ctx->buf[i]);
+  ws_free(ctx->ws);
+  for (Ws* w : ctx->batch_ws) {
+    ws_free(*w);
+    delete w;
+  }
   solve_cache_free(ctx);
+  tile_cache_free(ctx);
+  if (ctx->capture_stream) hipStreamDestroy(ctx->capture_stream);
   delete ctx;
 }
 
@@ -172,337 +150,6 @@ graver_status graver_kernel_basis(int32_t m, int32_t n, const int64_t* A, int32_
   if (m < 1 || n < 1 || n > 4096 || !A || !B_out || !d_out)
     return set_error(GRAVER_E_INVALID, "graver_kernel_basis: bad arguments");
   return kernel_basis_host(m, n, A, lll, B_out, d_out, P_out);
-}
-
-graver_status graver_extract(graver_ctx* ctx, const graver_problem* prob,
-                             const graver_extract_params* prm, graver_state* state,
-                             int8_t* keys_out, int64_t keys_cap, int64_t* count_out,
-                             graver_extract_stats* stats) {
-  if (!ctx || !prm || !count_out) return set_error(GRAVER_E_INVALID, "NULL argument");
-  hipSetDevice(ctx->device);
-  std::vector<int64_t> hl, hu;
-  graver_status st = validate_problem(ctx, prob, false, hl, hu);
-  if (st != GRAVER_OK) return st;
-  const int n = prob->n, d = prob->d, m = prob->m;
-  const int64_t N = prm->n_starts;
-  const int T = prm->iters;
-  if (d < 1 || d > n || !prob->B) return set_error(GRAVER_E_INVALID, "need a basis B with 1 <= d <= n");
-  if (N < 1 || N > (int64_t)1 << 30 || T < 0) return set_error(GRAVER_E_INVALID, "bad n_starts / iters");
-  if (prm->precision != GRAVER_FP64 && prm->precision != GRAVER_FP32 && prm->precision != GRAVER_BF16)
-    return set_error(GRAVER_E_INVALID, "unknown precision");
-  if (prm->polish_iters < 0) return set_error(GRAVER_E_INVALID, "polish_iters < 0");
-  if (prm->init_mode == 0 && !prob->P) return set_error(GRAVER_E_INVALID, "init_mode 0 needs P");
-  if (prm->init_mode == 1 && (!state || !state->z))
-    return set_error(GRAVER_E_INVALID, "init_mode 1 needs state->z");
-  if (prm->init_mode != 0 && prm->init_mode != 1) return set_error(GRAVER_E_INVALID, "bad init_mode");
-  if (prm->collect && (prm->pool_capacity < 1 || prm->pool_capacity > ((int64_t)1 << 31)))
-    return set_error(GRAVER_E_INVALID, "pool_capacity must be in [1, 2^31]");
-  if (prm->t0 < 0 || !(prm->beta1 >= 0 && prm->beta1 < 1) || !(prm->beta2 >= 0 && prm->beta2 < 1))
-    return set_error(GRAVER_E_INVALID, "bad Adam parameters");
-  if (prm->collect && (keys_cap < 0 || (keys_cap > 0 && !keys_out)))
-    return set_error(GRAVER_E_INVALID, "bad output buffer");
-
-  // B must be a kernel basis: A B = 0 exactly.  A's nonzeros (CSR) serve
-  // the exact check of the collected candidates.
-  std::vector<int32_t> csr_rp((size_t)m + 1, 0), csr_col;
-  std::vector<int64_t> csr_val;
-  {
-    std::vector<int64_t> hA, hB;
-    if ((st = copy_to_host(ctx, hA, prob->A, (size_t)m * n)) != GRAVER_OK) return st;
-    for (int i = 0; i < m; ++i) {
-      for (int j = 0; j < n; ++j) {
-        const int64_t av = hA[(size_t)i * n + j];
-        if (av <= -((int64_t)1 << 31) || av >= ((int64_t)1 << 31))
-          return set_error(GRAVER_E_OVERFLOW, "|A_ij| must be below 2^31");
-        if (av != 0) {
-          csr_col.push_back(j);
-          csr_val.push_back(av);
-        }
-      }
-      csr_rp[i + 1] = (int32_t)csr_col.size();
-    }
-    if ((st = copy_to_host(ctx, hB, prob->B, (size_t)n * d)) != GRAVER_OK) return st;
-    for (int i = 0; i < m; ++i)
-      for (int c = 0; c < d; ++c) {
-        __int128 s = 0;
-        for (int j = 0; j < n; ++j) s += (__int128)hA[(size_t)i * n + j] * hB[(size_t)j * d + c];
-        if (s != 0) return set_error(GRAVER_E_NOT_KERNEL, "A B != 0: B is not a kernel basis");
-      }
-  }
-
-  hipStream_t s = ctx->stream;
-  graver_extract_stats stt{};
-  stt.start_iterations = N * (int64_t)T;
-
-  // Bias corrections 1 - beta^t for t = t0+1 .. t0+T (host libm pow).
-  std::vector<double> hbc(2 * (size_t)std::max(T, 1));
-  for (int k = 0; k < T; ++k) {
-    double t = (double)prm->t0 + k + 1;
-    hbc[2 * k] = 1.0 - std::pow(prm->beta1, t);
-    hbc[2 * k + 1] = 1.0 - std::pow(prm->beta2, t);
-  }
-  double* dbc = (double*)ws_get(ctx, WS_BC, hbc.size() * sizeof(double), &st);
-  if (!dbc) return st;
-  HIP_TRY(hipMemcpyAsync(dbc, hbc.data(), hbc.size() * sizeof(double), hipMemcpyHostToDevice, s),
-          "copy bias corrections");
-
-  const size_t nd = (size_t)N * d;
-  double* z = (double*)ws_get(ctx, WS_Z, nd * sizeof(double), &st);
-  if (!z) return st;
-  double* mm = (double*)ws_get(ctx, WS_M, nd * sizeof(double), &st);
-  if (!mm) return st;
-  double* vv = (double*)ws_get(ctx, WS_V, nd * sizeof(double), &st);
-  if (!vv) return st;
-
-  // Pool.
-  PoolDev pool{};
-  pool.n = n;
-  pool.stride = key_stride(n);
-  uint64_t cap = prm->collect ? (uint64_t)prm->pool_capacity : 1;
-  uint64_t tsize = 1024;
-  while (tsize < 2 * cap) tsize <<= 1;
-  pool.cap = (uint32_t)std::min<uint64_t>(cap, 0xFFFFFFF0u);
-  pool.tmask = tsize - 1;
-  pool.keys = (int8_t*)ws_get(ctx, WS_POOL_KEYS, (size_t)pool.cap * pool.stride, &st);
-  if (!pool.keys) return st;
-  pool.table = (uint64_t*)ws_get(ctx, WS_POOL_TABLE, tsize * sizeof(uint64_t), &st);
-  if (!pool.table) return st;
-  pool.count = (uint32_t*)ws_get(ctx, WS_POOL_COUNT, 64, &st);
-  if (!pool.count) return st;
-  auto* counters = (unsigned long long*)ws_get(ctx, WS_COUNTERS, 64, &st);
-  if (!counters) return st;
-
-  {
-    EventTimer tm(s);
-    if (prm->init_mode == 0) {
-      double* g0 = (double*)ws_get(ctx, WS_G0, (size_t)N * n * sizeof(double), &st);
-      if (!g0) return st;
-      HIP_TRY(launch_init_box(s, n, d, N, prob->P, prob->l, prob->u, prm->seed, prm->first_start, g0, z),
-              "init kernels");
-      HIP_TRY(hipMemsetAsync(mm, 0, nd * sizeof(double), s), "clear m");
-      HIP_TRY(hipMemsetAsync(vv, 0, nd * sizeof(double), s), "clear v");
-    } else {
-      HIP_TRY(hipMemcpyAsync(z, state->z, nd * sizeof(double), hipMemcpyDeviceToDevice, s), "copy z");
-      if (state->m)
-        HIP_TRY(hipMemcpyAsync(mm, state->m, nd * sizeof(double), hipMemcpyDeviceToDevice, s), "copy m");
-      else
-        HIP_TRY(hipMemsetAsync(mm, 0, nd * sizeof(double), s), "clear m");
-      if (state->v)
-        HIP_TRY(hipMemcpyAsync(vv, state->v, nd * sizeof(double), hipMemcpyDeviceToDevice, s), "copy v");
-      else
-        HIP_TRY(hipMemsetAsync(vv, 0, nd * sizeof(double), s), "clear v");
-    }
-    HIP_TRY(launch_pool_clear(s, pool), "pool clear");
-    HIP_TRY(hipMemsetAsync(counters, 0, 64, s), "clear counters");
-    stt.ms_init = tm.stop_ms();
-  }
-
-  DescentArgs da{};
-  da.n = n;
-  da.d = d;
-  da.N = (int32_t)N;
-  da.T = T;
-  da.B = prob->B;
-  da.l = prob->l;
-  da.u = prob->u;
-  da.lr = prm->lr;
-  da.beta1 = prm->beta1;
-  da.beta2 = prm->beta2;
-  da.eps = prm->eps;
-  da.lambda1 = prm->lambda1;
-  da.lambda2 = prm->lambda2;
-  da.one_minus_b1 = 1.0 - prm->beta1;
-  da.one_minus_b2 = 1.0 - prm->beta2;
-  da.bc = dbc;
-  da.collect = prm->collect;
-  da.bf16_iters = prm->precision == GRAVER_BF16 ? std::max(0, T - prm->polish_iters) : 0;
-  da.lim_uniform = (int32_t)(hu[0] - hl[0]);
-  for (int i = 1; i < n; ++i)
-    if (hu[i] - hl[i] != hu[0] - hl[0]) da.lim_uniform = -1;
-
-  {
-    if (prm->precision == GRAVER_FP64) {
-      double* rp = (double*)ws_get(ctx, WS_RPREV, nd * sizeof(double), &st);
-      if (!rp) return st;
-      int8_t* sg = (int8_t*)ws_get(ctx, WS_SIGN, (size_t)N * n, &st);
-      if (!sg) return st;
-      int8_t* ks = (int8_t*)ws_get(ctx, WS_KEYSCRATCH, (size_t)N * pool.stride, &st);
-      if (!ks) return st;
-      HIP_TRY(hipMemsetAsync(rp, 0xFF, nd * sizeof(double), s), "rprev = NaN");
-      EventTimer tm(s);
-      if (T > 0) HIP_TRY(launch_descent_fp64(s, da, z, mm, vv, rp, sg, ks, pool, counters), "descent fp64");
-      stt.ms_descent = tm.stop_ms();
-    } else {
-      const bool small = descent_f32_supported(n, d);
-      if (!small && !descent_big_supported(n, d))
-        return set_error(GRAVER_E_INVALID, "the MFMA descent supports n <= 1024 and d <= 1024");
-      // |B_ij| <= 256 makes every bf16 operand exact; row l1 norms bound the
-      // exact range of the candidate map.
-      int* rowl1 = (int*)ws_get(ctx, WS_MISC, 64, &st);
-      if (!rowl1) return st;
-      float* Bp = nullptr;
-      float* BTp = nullptr;
-      unsigned char* img = nullptr;
-      if (small) {
-        Bp = (float*)ws_get(ctx, WS_MF_B, f32_pack_floats(n, d) * sizeof(float), &st);
-        if (!Bp) return st;
-        BTp = (float*)ws_get(ctx, WS_MF_BT, f32_pack_floats(n, d) * sizeof(float), &st);
-        if (!BTp) return st;
-        HIP_TRY(launch_f32_pack(s, n, d, prob->B, Bp, BTp, rowl1), "pack basis");
-      } else {
-        img = (unsigned char*)ws_get(ctx, WS_MF_B, big_image_bytes(n, d), &st);
-        if (!img) return st;
-        HIP_TRY(launch_big_pack(s, n, d, prob->B, img), "pack basis");
-        HIP_TRY(launch_rowl1(s, n, d, prob->B, rowl1), "row norms");
-      }
-      int hrow[2] = {0, 0};
-      HIP_TRY(hipMemcpyAsync(hrow, rowl1, 2 * sizeof(int), hipMemcpyDeviceToHost, s), "row l1");
-      HIP_TRY(hipStreamSynchronize(s), "sync");
-      if (hrow[1] > 256)
-        return set_error(GRAVER_E_INVALID, "the MFMA descent needs |B_ij| <= 256 (exact bf16 operands)");
-      // large bases: candidates B r with |r_j| <= 256 must stay exact in fp32
-      if (!small && (int64_t)hrow[0] * 256 >= (int64_t)1 << 24)
-        return set_error(GRAVER_E_INVALID, "the MFMA descent needs every row l1 norm of B below 65536");
-      const float zrange = (float)std::min(1073741824.0, std::floor(16777216.0 / std::max(hrow[0], 1)));
-      const int DBlay = small ? (d + 15) / 16 : descent_big_dbp(d);
-      const size_t sfloats = small ? f32_state_floats(n, d, N) : big_state_floats(d, N);
-      float* fstate = (float*)ws_get(ctx, WS_MF_STATE, sfloats * sizeof(float), &st);
-      if (!fstate) return st;
-      int8_t* kscr = nullptr;
-      if (!small) {
-        kscr = (int8_t*)ws_get(ctx, WS_KEYSCRATCH, ((size_t)N + 64) * pool.stride, &st);
-        if (!kscr) return st;
-      }
-      HIP_TRY(launch_state_io_db(s, d, DBlay, N, fstate, z, mm, vv, 1), "state in");
-      LogDev lg{};
-      lg.stride = pool.stride;
-      lg.cap = prm->collect ? pool.cap : 0u;
-      lg.rows = (int8_t*)ws_get(ctx, WS_LOG, (size_t)std::max<uint32_t>(lg.cap, 1) * pool.stride, &st);
-      if (!lg.rows) return st;
-      lg.count = (uint32_t*)ws_get(ctx, WS_LOG_COUNT, 64, &st);
-      if (!lg.count) return st;
-      const size_t sbytes = sfloats * sizeof(float);
-      float* fbak = (float*)ws_get(ctx, WS_MF_BAK, sbytes, &st);
-      if (!fbak) return st;
-      unsigned long long* cbak = (unsigned long long*)ws_get(ctx, WS_MISC2, 64, &st);
-      if (!cbak) return st;
-      da.log = lg;
-      const int bf16_total = da.bf16_iters;
-      // The candidate log holds pool_capacity rows per launch.  A launch whose
-      // log overflows is rolled back (state and counters) and replayed in two
-      // halves, so every candidate reaches the pool.
-      int done = 0, chunk = T;
-      while (done < T) {
-        int c = std::min(chunk, T - done);
-        // a launch of the large-basis kernel uses a single forward form
-        if (!small && done < bf16_total) c = std::min(c, bf16_total - done);
-        DescentArgs dc = da;
-        dc.T = c;
-        dc.bc = dbc + 2 * (size_t)done;
-        dc.bf16_iters = std::max(0, std::min(c, bf16_total - done));
-        HIP_TRY(hipMemcpyAsync(fbak, fstate, sbytes, hipMemcpyDeviceToDevice, s), "state backup");
-        HIP_TRY(hipMemcpyAsync(cbak, counters, 64, hipMemcpyDeviceToDevice, s), "counter backup");
-        HIP_TRY(hipMemsetAsync(lg.count, 0, 64, s), "clear log count");
-        EventTimer tm(s);
-        if (small)
-          HIP_TRY(launch_descent_f32(s, dc, Bp, BTp, fstate, pool, counters, zrange), "descent mfma");
-        else
-          HIP_TRY(launch_descent_big(s, dc, img, fstate, kscr, counters), "descent mfma (large)");
-        stt.ms_descent += tm.stop_ms();
-        uint32_t lflag[2] = {0, 0};
-        HIP_TRY(hipMemcpyAsync(lflag, lg.count, sizeof(lflag), hipMemcpyDeviceToHost, s), "log flag");
-        HIP_TRY(hipStreamSynchronize(s), "sync");
-        if (lflag[1]) {
-          if (c == 1) return set_error(GRAVER_E_POOL_FULL, "one iteration yields more candidates than pool_capacity");
-          HIP_TRY(hipMemcpyAsync(fstate, fbak, sbytes, hipMemcpyDeviceToDevice, s), "state rollback");
-          HIP_TRY(hipMemcpyAsync(counters, cbak, 64, hipMemcpyDeviceToDevice, s), "counter rollback");
-          chunk = std::max(1, c / 2);
-          continue;
-        }
-        if (prm->collect) {
-          HIP_TRY(launch_log_insert(s, lg, pool), "log insert");
-          // stop as soon as the pool cannot hold the distinct candidates
-          uint32_t pf[3] = {0, 0, 0};
-          HIP_TRY(hipMemcpyAsync(pf, pool.count, sizeof(pf), hipMemcpyDeviceToHost, s), "pool flags");
-          HIP_TRY(hipStreamSynchronize(s), "sync");
-          if (pf[1]) return set_error(GRAVER_E_POOL_FULL, "more distinct candidates than pool_capacity");
-          if (pf[2]) return set_error(GRAVER_E_POOL_FULL, "hash probe limit reached");
-        }
-        done += c;
-      }
-      HIP_TRY(launch_state_io_db(s, d, DBlay, N, fstate, z, mm, vv, 0), "state out");
-
-    }
-  }
-  HIP_TRY(hipGetLastError(), "descent launch");
-
-  // Counters and pool status.
-  unsigned long long hc[C_NCOUNTERS] = {};
-  uint32_t hp[3] = {};
-  HIP_TRY(hipMemcpyAsync(hc, counters, sizeof(hc), hipMemcpyDeviceToHost, s), "counters");
-  HIP_TRY(hipMemcpyAsync(hp, pool.count, sizeof(hp), hipMemcpyDeviceToHost, s), "pool count");
-  HIP_TRY(hipStreamSynchronize(s), "descent");
-  stt.emit_events = (int64_t)hc[C_EMIT];
-  stt.inbox_events = (int64_t)hc[C_INBOX];
-  stt.out_of_range = (int64_t)hc[C_RANGE];
-
-  if (state) {
-    if (state->z && state->z != z)
-      HIP_TRY(hipMemcpyAsync(state->z, z, nd * sizeof(double), hipMemcpyDeviceToDevice, s), "z out");
-    if (state->m) HIP_TRY(hipMemcpyAsync(state->m, mm, nd * sizeof(double), hipMemcpyDeviceToDevice, s), "m out");
-    if (state->v) HIP_TRY(hipMemcpyAsync(state->v, vv, nd * sizeof(double), hipMemcpyDeviceToDevice, s), "v out");
-  }
-
-  *count_out = 0;
-  if (!prm->collect) {
-    if (stats) *stats = stt;
-    HIP_TRY(hipStreamSynchronize(s), "sync");
-    return GRAVER_OK;
-  }
-  if (hp[1]) return set_error(GRAVER_E_POOL_FULL, "more distinct candidates than pool_capacity");
-  if (hp[2]) return set_error(GRAVER_E_POOL_FULL, "hash probe limit reached");
-  uint32_t count = std::min<uint32_t>(hp[0], pool.cap);
-  stt.unique = count;
-
-  {
-    EventTimer tm(s);
-    unsigned int* bad = (unsigned int*)ws_get(ctx, WS_FLAGS, 64, &st);
-    if (!bad) return st;
-    const size_t nnz = csr_col.size();
-    const size_t ints = ((size_t)m + 1 + nnz + 1) / 2 * 2;  // int32 part, padded to 8 bytes
-    auto* csr = (int32_t*)ws_get(ctx, WS_V_CSR, ints * 4 + std::max<size_t>(nnz, 1) * 8, &st);
-    if (!csr) return st;
-    HIP_TRY(hipMemcpyAsync(csr, csr_rp.data(), csr_rp.size() * 4, hipMemcpyHostToDevice, s), "csr");
-    if (nnz) {
-      HIP_TRY(hipMemcpyAsync(csr + m + 1, csr_col.data(), nnz * 4, hipMemcpyHostToDevice, s), "csr");
-      HIP_TRY(hipMemcpyAsync(csr + ints, csr_val.data(), nnz * 8, hipMemcpyHostToDevice, s), "csr");
-    }
-    HIP_TRY(launch_verify(s, pool, count, m, csr, csr + m + 1, reinterpret_cast<const int64_t*>(csr + ints), bad),
-            "verify");
-    unsigned int hbad = 0;
-    HIP_TRY(hipMemcpyAsync(&hbad, bad, sizeof(hbad), hipMemcpyDeviceToHost, s), "verify flag");
-    stt.ms_verify = tm.stop_ms();
-    if (hbad) return set_error(GRAVER_E_NOT_KERNEL, "a collected candidate fails A g = 0");
-    stt.verified = count;
-  }
-  if ((int64_t)count > keys_cap) {
-    if (stats) *stats = stt;
-    *count_out = count;
-    return set_error(GRAVER_E_CAPACITY, "keys_cap too small for the collected set");
-  }
-  {
-    EventTimer tm(s);
-    uint32_t p2 = 1024;
-    while (p2 < count) p2 <<= 1;
-    uint32_t* idx = (uint32_t*)ws_get(ctx, WS_SORT_IDX, (size_t)p2 * sizeof(uint32_t), &st);
-    if (!idx) return st;
-    HIP_TRY(launch_sort_keys(s, pool.keys, pool.stride, n, count, idx, nullptr, 0, nullptr), "sort");
-    HIP_TRY(launch_gather_keys(s, pool.keys, pool.stride, n, idx, count, keys_out, n), "gather");
-    stt.ms_sort = tm.stop_ms();
-  }
-  *count_out = count;
-  if (stats) *stats = stt;
-  return GRAVER_OK;
 }
 
 graver_status graver_filter(graver_ctx* ctx, int32_t n, const int8_t* keys_in, int64_t count_in,

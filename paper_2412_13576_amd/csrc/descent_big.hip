@@ -27,6 +27,9 @@
 // exact in bf16); the binary32 forward widens the operands in registers.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <vector>
+
 #include "graver_internal.h"
 
 namespace graver {
@@ -41,20 +44,10 @@ constexpr int kBigLogChunk = 64;
 
 inline int blk16(int x) { return (x + 15) / 16; }
 
-// Column split: CS waves per start group, DBPW column blocks per wave.
-struct BigShape {
-  int cs, dbpw;
-};
-
-// Smallest split whose waves hold at most 12 column blocks (wider waves
-// exceed the register file); 16 blocks per wave only beyond d = 768.
-BigShape big_shape(int d) {
-  const int db = blk16(d);
-  static const BigShape kShapes[] = {{1, 8}, {1, 12}, {2, 8}, {2, 12}, {4, 8}, {4, 12}, {4, 16}};
-  for (const BigShape& sh : kShapes)
-    if (sh.cs * sh.dbpw >= db) return sh;
-  return {0, 0};
-}
+// Shapes with an instantiated kernel, in order of preference: the smallest
+// split whose waves hold at most 12 column blocks (wider waves exceed the
+// register file); 16 blocks per wave only beyond d = 768.
+constexpr BigShape kShapes[] = {{1, 8}, {1, 12}, {2, 8}, {2, 12}, {4, 8}, {4, 12}, {4, 16}};
 
 inline int64_t big_waves(int64_t N) {
   int64_t w = (N + 15) / 16;
@@ -137,7 +130,10 @@ struct BigArgs {
   int64_t per;
   int8_t* scratch;  // one key row per start
   int stride;
+  unsigned long long* counters;
 };
+
+inline size_t desc_table_bytes(int count) { return ((size_t)count * sizeof(BigArgs) + 255) / 256 * 256; }
 
 __device__ __forceinline__ void zero_rows_big(const LogDev& log, uint32_t first, uint32_t rows, int lane) {
   const int dw = log.stride / 4;
@@ -145,8 +141,24 @@ __device__ __forceinline__ void zero_rows_big(const LogDev& log, uint32_t first,
   for (uint32_t t = lane; t < rows * (uint32_t)dw; t += 64) base[t] = 0u;
 }
 
+// The grid covers the start groups of every instance of the launch: block
+// b belongs to the instance i with cum[i] <= b < cum[i + 1].
 template <int CS, int DBPW, bool BF16F>
-__global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(BigArgs g, unsigned long long* counters) {
+__global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(const BigArgs* __restrict__ descs,
+                                                                const int64_t* __restrict__ cum, int count) {
+  int inst = 0;
+  {
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (cum[mid] <= (int64_t)blockIdx.x) lo = mid;
+      else hi = mid - 1;
+    }
+    inst = lo;
+  }
+  const BigArgs& g = descs[inst];
+  const int64_t bx = (int64_t)blockIdx.x - cum[inst];
+  unsigned long long* counters = g.counters;
   const DescentArgs& a = g.a;
   constexpr int DBT = CS * DBPW;                        // column blocks of the image
   constexpr int kChunkU4 = DBT * 64;                    // uint4 per row-block chunk
@@ -165,8 +177,8 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(BigArgs g, unsig
   const int cs = wid % CS;       // column slice of this wave
   const int gw0 = wid - cs;      // first wave of this start group
   const bool lead = cs == 0;     // the slice that emits candidates
-  const int64_t sgroup = (int64_t)blockIdx.x * (kWaves / CS) + wid / CS;
-  const int64_t w = (int64_t)blockIdx.x * kWaves + wid;  // = sgroup * CS + cs
+  const int64_t sgroup = bx * (kWaves / CS) + wid / CS;
+  const int64_t w = bx * kWaves + wid;  // = sgroup * CS + cs
   const int64_t sidx = sgroup * 16 + sl;
   const bool svalid = sidx < a.N;
   const int NB = g.NB;
@@ -250,8 +262,9 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(BigArgs g, unsig
       inrange = f_and ? 1 : 0;
     }
     // block-uniform (the row-block loop below has block barriers, and the
-    // final pass exits the loop when no wave of the block needs it)
-    const bool needg = a.collect && k > 0 && __syncthreads_or((changed && alive) ? 1 : 0) != 0;
+    // final pass exits the loop when no wave of the block needs it).  The
+    // barrier is taken on every iteration: it also publishes row block 0.
+    const bool needg = __syncthreads_or((a.collect && k > 0 && changed && alive) ? 1 : 0) != 0;
     if (!descend && !needg) break;
     // rounded coordinates of the current iterate as exact bf16 operands
     shortx4 rp[DBPW];
@@ -504,66 +517,107 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(BigArgs g, unsig
 }
 
 template <int CS, int DBPW, bool BF16F>
-hipError_t launch_big_t(hipStream_t s, const BigArgs& g, unsigned long long* counters) {
-  const int64_t groups = (g.a.N + 15) / 16;
-  const int64_t per_block = kWaves / CS;
-  const int64_t blocks = (groups + per_block - 1) / per_block;
-  const size_t shmem = (size_t)2 * CS * DBPW * 64 * 16 + (size_t)16 * g.NB * sizeof(int);
+hipError_t launch_big_t(hipStream_t s, const void* dev_desc, int count, int64_t total_blocks, int max_nb) {
+  const size_t shmem = (size_t)2 * CS * DBPW * 64 * 16 + (size_t)16 * max_nb * sizeof(int);
   auto kern = k_descent_big<CS, DBPW, BF16F>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * kWaves), shmem, s, g, counters);
+  const BigArgs* descs = static_cast<const BigArgs*>(dev_desc);
+  const int64_t* cum = reinterpret_cast<const int64_t*>(static_cast<const unsigned char*>(dev_desc) +
+                                                         desc_table_bytes(count));
+  hipLaunchKernelGGL(kern, dim3((unsigned)total_blocks), dim3(64 * kWaves), shmem, s, descs, cum, count);
   return hipGetLastError();
 }
 
 template <bool BF16F>
-hipError_t launch_big_shape(hipStream_t s, const BigArgs& g, BigShape sh, unsigned long long* counters) {
+hipError_t launch_big_shape(hipStream_t s, BigShape sh, const void* dev_desc, int count, int64_t total_blocks,
+                            int max_nb) {
   switch (sh.cs * 100 + sh.dbpw) {
-    case 108: return launch_big_t<1, 8, BF16F>(s, g, counters);
-    case 112: return launch_big_t<1, 12, BF16F>(s, g, counters);
-    case 208: return launch_big_t<2, 8, BF16F>(s, g, counters);
-    case 212: return launch_big_t<2, 12, BF16F>(s, g, counters);
-    case 408: return launch_big_t<4, 8, BF16F>(s, g, counters);
-    case 412: return launch_big_t<4, 12, BF16F>(s, g, counters);
-    case 416: return launch_big_t<4, 16, BF16F>(s, g, counters);
+    case 108: return launch_big_t<1, 8, BF16F>(s, dev_desc, count, total_blocks, max_nb);
+    case 112: return launch_big_t<1, 12, BF16F>(s, dev_desc, count, total_blocks, max_nb);
+    case 208: return launch_big_t<2, 8, BF16F>(s, dev_desc, count, total_blocks, max_nb);
+    case 212: return launch_big_t<2, 12, BF16F>(s, dev_desc, count, total_blocks, max_nb);
+    case 408: return launch_big_t<4, 8, BF16F>(s, dev_desc, count, total_blocks, max_nb);
+    case 412: return launch_big_t<4, 12, BF16F>(s, dev_desc, count, total_blocks, max_nb);
+    case 416: return launch_big_t<4, 16, BF16F>(s, dev_desc, count, total_blocks, max_nb);
   }
   return hipErrorInvalidValue;
 }
 
 }  // namespace
 
-bool descent_big_supported(int n, int d) { return n <= 1024 && d <= n && big_shape(d).cs > 0; }
-bool descent_big_bf16_supported(int d) { return big_shape(d).cs > 0; }
-int descent_big_dbp(int d) {
-  BigShape sh = big_shape(d);
-  return sh.cs * sh.dbpw;
+BigShape big_shape_default(int d) {
+  const int db = blk16(d);
+  for (const BigShape& sh : kShapes)
+    if (sh.cs * sh.dbpw >= db) return sh;
+  return BigShape{};
 }
-size_t big_image_bytes(int n, int d) { return (size_t)blk16(n) * descent_big_dbp(d) * 64 * 16; }
-size_t big_state_floats(int d, int64_t N) { return 3 * (size_t)big_waves(N) * 4 * descent_big_dbp(d) * 64; }
 
-hipError_t launch_big_pack(hipStream_t s, int n, int d, const int64_t* B, unsigned char* img) {
-  int NB = blk16(n), DBT = descent_big_dbp(d);
+bool big_shape_fits(BigShape sh, int d) {
+  for (const BigShape& k : kShapes)
+    if (k.cs == sh.cs && k.dbpw == sh.dbpw) return sh.cs * sh.dbpw >= blk16(d);
+  return false;
+}
+
+// Instantiated shapes that hold d with at most twice the needed column
+// blocks (the autotuner's choices), in order of preference.
+int big_shape_candidates(int d, BigShape* out, int cap) {
+  const int db = blk16(d);
+  int k = 0;
+  for (const BigShape& sh : kShapes)
+    if (sh.cs * sh.dbpw >= db && sh.cs * sh.dbpw <= 2 * db + 8 && k < cap) out[k++] = sh;
+  return k;
+}
+
+bool descent_big_supported(int n, int d) { return n <= 1024 && d <= n && big_shape_default(d).cs > 0; }
+size_t big_image_bytes(int n, BigShape sh) { return (size_t)blk16(n) * sh.cs * sh.dbpw * 64 * 16; }
+size_t big_state_floats(BigShape sh, int64_t N) { return 3 * (size_t)big_waves(N) * 4 * sh.cs * sh.dbpw * 64; }
+
+hipError_t launch_big_pack(hipStream_t s, int n, int d, BigShape sh, const int64_t* B, unsigned char* img) {
+  int NB = blk16(n), DBT = sh.cs * sh.dbpw;
   int total = NB * DBT * 64;
   hipLaunchKernelGGL(k_pack_big, dim3((total + 255) / 256), dim3(256), 0, s, n, d, NB, DBT, B, img);
   return hipGetLastError();
 }
 
-hipError_t launch_descent_big(hipStream_t s, const DescentArgs& a, const unsigned char* img, float* state,
-                              int8_t* scratch, unsigned long long* counters) {
-  const BigShape sh = big_shape(a.d);
-  if (sh.cs == 0) return hipErrorInvalidValue;
-  BigArgs g{};
-  g.a = a;
-  g.NB = blk16(a.n);
-  g.img = img;
-  g.z = state;
-  // the state layout is that of DBT = cs * dbpw column blocks per start group
-  g.per = big_waves(a.N) * 4 * (sh.cs * sh.dbpw) * 64;
-  g.scratch = scratch;
-  g.stride = key_stride(a.n);
-  // the whole launch uses one forward form: bf16 when a.bf16_iters covers it
-  const bool bf = a.bf16_iters >= a.T && a.T > 0;
-  return bf ? launch_big_shape<true>(s, g, sh, counters) : launch_big_shape<false>(s, g, sh, counters);
+size_t big_desc_prepare(BigShape sh, const BigJob* jobs, int count, std::vector<unsigned char>& host,
+                        int64_t* total_blocks, int* max_nb) {
+  const size_t tb = desc_table_bytes(count);
+  host.assign(tb + (size_t)(count + 1) * sizeof(int64_t), 0);
+  BigArgs* descs = reinterpret_cast<BigArgs*>(host.data());
+  int64_t* cum = reinterpret_cast<int64_t*>(host.data() + tb);
+  const int DBT = sh.cs * sh.dbpw;
+  int64_t blocks = 0;
+  int nbmax = 1;
+  for (int i = 0; i < count; ++i) {
+    const BigJob& j = jobs[i];
+    BigArgs g{};
+    g.a = j.a;
+    g.NB = blk16(j.a.n);
+    g.img = j.img;
+    g.z = j.state;
+    // the state layout is that of DBT column blocks per start group
+    g.per = big_waves(j.a.N) * 4 * DBT * 64;
+    g.scratch = j.scratch;
+    g.stride = key_stride(j.a.n);
+    g.counters = j.counters;
+    descs[i] = g;
+    cum[i] = blocks;
+    const int64_t groups = ((int64_t)j.a.N + 15) / 16;
+    blocks += (groups + kWaves / sh.cs - 1) / (kWaves / sh.cs);
+    nbmax = std::max(nbmax, g.NB);
+  }
+  cum[count] = blocks;
+  *total_blocks = blocks;
+  *max_nb = nbmax;
+  return host.size();
+}
+
+hipError_t launch_descent_big(hipStream_t s, BigShape sh, bool bf16_forward, const void* dev_desc, int count,
+                              int64_t total_blocks, int max_nb) {
+  if (count < 1 || total_blocks < 1) return hipSuccess;
+  return bf16_forward ? launch_big_shape<true>(s, sh, dev_desc, count, total_blocks, max_nb)
+                      : launch_big_shape<false>(s, sh, dev_desc, count, total_blocks, max_nb);
 }
 
 }  // namespace graver

@@ -6,24 +6,75 @@
 
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "graver.h"
+
+namespace graver {
+// A set of device workspace buffers, one per slot, each grown on demand.
+struct Ws {
+  static constexpr int kSlots = 72;
+  void* buf[kSlots] = {};
+  size_t cap[kSlots] = {};
+};
+}  // namespace graver
 
 struct graver_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
-  static constexpr int kSlots = 64;
-  void* buf[kSlots] = {};
-  size_t cap[kSlots] = {};
-  void* host_pinned = nullptr;  // small pinned staging area
-  size_t host_pinned_cap = 0;
-  void* solve_cache = nullptr;  // graver::SolveCache (bases and filtered sets by (A, u - l))
+  graver::Ws ws;                       // workspace of single-instance calls
+  std::vector<graver::Ws*> batch_ws;   // one per instance of a batched call
+  void* solve_cache = nullptr;         // graver::SolveCache (bases and filtered sets by (A, u - l))
+  void* tile_cache = nullptr;          // graver::TileCache (autotuned large-kernel shapes)
+  hipStream_t capture_stream = nullptr;  // private stream for graph capture (default priority)
 };
 
 namespace graver {
 
 graver_status set_error(graver_status s, const std::string& msg);
 graver_status hip_error(hipError_t e, const char* what);
+
+#define HIP_TRY(expr, what)                               \
+  do {                                                    \
+    hipError_t e_ = (expr);                               \
+    if (e_ != hipSuccess) return hip_error(e_, what);     \
+  } while (0)
+
+template <class T>
+graver_status copy_to_host(graver_ctx* ctx, std::vector<T>& dst, const T* src, size_t count) {
+  dst.resize(count);
+  if (count == 0) return GRAVER_OK;
+  HIP_TRY(hipMemcpyAsync(dst.data(), src, count * sizeof(T), hipMemcpyDeviceToHost, ctx->stream),
+          "device to host copy");
+  HIP_TRY(hipStreamSynchronize(ctx->stream), "stream synchronize");
+  return GRAVER_OK;
+}
+
+// Device time between construction and stop_ms() on one stream.
+struct EventTimer {
+  hipEvent_t a = nullptr, b = nullptr;
+  hipStream_t s;
+  explicit EventTimer(hipStream_t st) : s(st) {
+    hipEventCreate(&a);
+    hipEventCreate(&b);
+    hipEventRecord(a, s);
+  }
+  double stop_ms() {
+    float ms = 0.f;
+    hipEventRecord(b, s);
+    hipEventSynchronize(b);
+    hipEventElapsedTime(&ms, a, b);
+    return ms;
+  }
+  ~EventTimer() {
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+  }
+};
+
+graver_status validate_problem(graver_ctx* ctx, const graver_problem* p, bool need_b,
+                               std::vector<int64_t>& hl, std::vector<int64_t>& hu);
+void ws_free(Ws& w);
 
 // Workspace slots (each grows on demand and is reused across calls).
 enum Slot : int {
@@ -36,11 +87,12 @@ enum Slot : int {
   WS_F_CODE, WS_F_HIST, WS_F_OFF, WS_F_CUR, WS_F_BL, WS_A_QFLAG, WS_LOG, WS_LOG_COUNT, WS_MF_BAK, WS_MISC2,
   WS_I_X, WS_I_M, WS_I_V, WS_I_R, WS_I_G,
   WS_S_KEYS, WS_S_F, WS_S_SOL, WS_S_FEAS, WS_S_IDX, WS_S_STARTS, WS_S_X, WS_S_FV, WS_S_STEPS, WS_S_B, WS_S_P,
-  WS_V_CSR,
+  WS_V_CSR, WS_BIG_DESC,
   WS_END
 };
-static_assert(WS_END <= graver_ctx::kSlots, "too many workspace slots");
+static_assert(WS_END <= Ws::kSlots, "too many workspace slots");
 void* ws_get(graver_ctx* ctx, int slot, size_t bytes, graver_status* st);
+void* ws_get(graver_ctx* ctx, Ws& w, int slot, size_t bytes, graver_status* st);
 
 graver_status kernel_basis_host(int32_t m, int32_t n, const int64_t* A, int32_t do_lll,
                                 int64_t* B_out, int32_t* d_out, double* P_out);
@@ -96,6 +148,7 @@ struct InitArgs {
 hipError_t launch_gather_rows_i64(hipStream_t s, const int64_t* src, int n, const int32_t* idx, int64_t cnt,
                                   int64_t* dst);
 void solve_cache_free(graver_ctx* ctx);
+void tile_cache_free(graver_ctx* ctx);
 
 hipError_t launch_init_sol(hipStream_t s, const InitArgs& a, const double* x0, uint64_t seed, int64_t first,
                            double* X, double* M, double* V, double* R, double* gscratch, int64_t* xr,
@@ -120,17 +173,38 @@ hipError_t launch_f32_state_io(hipStream_t s, int n, int d, int64_t N, float* st
 
 hipError_t launch_state_io_db(hipStream_t s, int d, int DB, int64_t N, float* state, double* z, double* m,
                               double* v, int to_device);
+// Large-basis kernel: a start group's coordinates split over cs waves of
+// dbpw 16-column blocks each (image and state layouts use cs * dbpw blocks).
+struct BigShape {
+  int cs = 0, dbpw = 0;
+};
+BigShape big_shape_default(int d);
+bool big_shape_fits(BigShape sh, int d);  // an instantiated shape with cs * dbpw * 16 >= d
+int big_shape_candidates(int d, BigShape* out, int cap);
 bool descent_big_supported(int n, int d);
-bool descent_big_bf16_supported(int d);
 hipError_t launch_rowl1(hipStream_t s, int n, int d, const int64_t* B, int* rowl1);
-int descent_big_dbp(int d);
-size_t big_image_bytes(int n, int d);
-size_t big_state_floats(int d, int64_t N);
-hipError_t launch_big_pack(hipStream_t s, int n, int d, const int64_t* B, unsigned char* img);
-hipError_t launch_descent_big(hipStream_t s, const DescentArgs& a, const unsigned char* img, float* state,
-                              int8_t* scratch, unsigned long long* counters);
+size_t big_image_bytes(int n, BigShape sh);
+size_t big_state_floats(BigShape sh, int64_t N);
+hipError_t launch_big_pack(hipStream_t s, int n, int d, BigShape sh, const int64_t* B, unsigned char* img);
+// One instance of a (possibly batched) large-kernel launch.
+struct BigJob {
+  DescentArgs a;
+  const unsigned char* img;
+  float* state;
+  int8_t* scratch;
+  unsigned long long* counters;
+};
+// Descriptor table of a launch over `count` jobs of one shape: host image
+// (kept alive by the caller until the stream has consumed it) and its size.
+size_t big_desc_prepare(BigShape sh, const BigJob* jobs, int count, std::vector<unsigned char>& host,
+                        int64_t* total_blocks, int* max_nb);
+// One grid over every job's start groups; the table must already be on the device.
+hipError_t launch_descent_big(hipStream_t s, BigShape sh, bool bf16_forward, const void* dev_desc, int count,
+                              int64_t total_blocks, int max_nb);
 
 hipError_t launch_pool_clear(hipStream_t s, PoolDev p);
+// p[0 .. n) = value (a kernel, so it may be captured in a graph)
+hipError_t launch_fill_u64(hipStream_t s, uint64_t* p, uint64_t n, uint64_t value);
 hipError_t launch_log_insert(hipStream_t s, LogDev log, PoolDev pool);
 hipError_t launch_verify(hipStream_t s, PoolDev p, uint32_t count, int m, const int32_t* rp, const int32_t* col,
                          const int64_t* val, unsigned int* bad);

@@ -15,6 +15,13 @@ __global__ void k_fill_u64(uint64_t* p, uint64_t n, uint64_t value) {
   for (; i < n; i += stride) p[i] = value;
 }
 
+hipError_t launch_fill_u64(hipStream_t s, uint64_t* p, uint64_t n, uint64_t value) {
+  int blocks = (int)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_fill_u64, dim3(blocks), dim3(256), 0, s, p, n, value);
+  return hipGetLastError();
+}
+
 hipError_t launch_pool_clear(hipStream_t s, PoolDev p) {
   uint64_t n = p.tmask + 1;
   int blocks = (int)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);

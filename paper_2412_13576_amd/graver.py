@@ -26,7 +26,8 @@ STATUS = {0: "OK", -1: "E_INVALID", -2: "E_INFEASIBLE_START", -3: "E_NOT_KERNEL"
 
 EXPORTED = ["graver_ctx_create", "graver_ctx_destroy", "graver_ctx_set_stream", "graver_last_error",
             "graver_status_string", "graver_kernel_basis", "graver_extract", "graver_filter",
-            "graver_augment", "graver_init_solutions", "graver_solve", "graver_lift_inequalities"]
+            "graver_augment", "graver_init_solutions", "graver_solve", "graver_lift_inequalities",
+            "graver_extract_batch"]
 
 
 class GraverError(RuntimeError):
@@ -77,6 +78,18 @@ class InitParams(C.Structure):
     _fields_ = [("n_starts", C.c_int64), ("iters", C.c_int32), ("init_mode", C.c_int32),
                 ("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
                 ("lambda3", C.c_double), ("seed", C.c_uint64), ("first_start", C.c_int64)]
+
+
+class BatchParams(C.Structure):
+    _fields_ = [("autotune", C.c_int32), ("use_graph", C.c_int32)]
+
+
+class BatchStats(C.Structure):
+    _fields_ = [("ms_descent", C.c_double), ("launches", C.c_int32), ("replays", C.c_int32),
+                ("graphs", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class SolveParams(C.Structure):
@@ -131,9 +144,12 @@ def lib():
                                                C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
                                                C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                                C.c_void_p]
+        L.graver_extract_batch.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                           C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                           C.POINTER(BatchParams), C.POINTER(BatchStats)]
         for name in ("graver_ctx_create", "graver_ctx_set_stream", "graver_kernel_basis",
                      "graver_extract", "graver_filter", "graver_augment", "graver_init_solutions",
-                     "graver_solve", "graver_lift_inequalities"):
+                     "graver_solve", "graver_lift_inequalities", "graver_extract_batch"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -348,3 +364,30 @@ def lift_inequalities(A, b, l, u, G, h, B=None):
                                           None if Bc is None else Bc.ctypes.data, A2.ctypes.data, b2.ctypes.data,
                                           l2.ctypes.data, u2.ctypes.data, None if Bt is None else Bt.ctypes.data))
     return A2, b2, l2, u2, Bt
+
+
+def extract_batch(ctx: Context, probs, params, states=None, autotune=False, use_graph=False, keys_caps=None):
+    """graver_extract_batch.  probs: list of DeviceProblem; params: list of
+    ExtractParams; states: optional list of state dicts (or None entries).
+    Returns (list of key tensors, list of stats dicts, batch stats dict)."""
+    import torch
+    cnt = len(probs)
+    pcs = (Problem * cnt)(*[p.c() for p in probs])
+    prm = (ExtractParams * cnt)(*params)
+    caps = [p.pool_capacity for p in params] if keys_caps is None else list(keys_caps)
+    keys = [torch.empty((max(c, 1), pr.A.shape[1]), dtype=torch.int8, device=pr.A.device) for c, pr in zip(caps, probs)]
+    kptr = (C.c_void_p * cnt)(*[k.data_ptr() for k in keys])
+    kcap = (C.c_int64 * cnt)(*caps)
+    out = (C.c_int64 * cnt)()
+    stt = (ExtractStats * cnt)()
+    st_structs = None
+    st_ptrs = None
+    if states is not None:
+        st_structs = [None if st is None else State(_ptr(st.get("z")), _ptr(st.get("m")), _ptr(st.get("v")))
+                      for st in states]
+        st_ptrs = (C.c_void_p * cnt)(*[None if x is None else C.addressof(x) for x in st_structs])
+    bp = BatchParams(int(autotune), int(use_graph))
+    bs = BatchStats()
+    _check(lib().graver_extract_batch(ctx.h, cnt, C.byref(pcs), C.byref(prm), st_ptrs, kptr, kcap, out,
+                                      C.byref(stt), C.byref(bp), C.byref(bs)))
+    return [k[: out[i]] for i, k in enumerate(keys)], [stt[i].as_dict() for i in range(cnt)], bs.as_dict()
