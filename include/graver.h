@@ -337,6 +337,71 @@ graver_status graver_solve(graver_ctx* ctx, const graver_problem* prob, const gr
                            const graver_solve_params* params, int64_t* x_best, double* f_best,
                            graver_solve_stats* stats);
 
+/* ---- serving ----------------------------------------------------------- */
+
+typedef struct graver_server graver_server;
+
+typedef struct {
+  int32_t device;
+  int64_t hbm_budget;    /* bytes of device memory admitted requests may hold  */
+  int32_t max_batch;     /* requests per batched extraction                     */
+  int32_t gpu_workers;   /* concurrent batches (each on its own stream)         */
+  int32_t host_threads;  /* kernel-basis threads                                */
+  int32_t autotune;      /* graver_batch_params.autotune                        */
+  int32_t use_graph;     /* graver_batch_params.use_graph                       */
+  int32_t batch_window_us; /* a worker that admitted fewer than max_batch requests
+                            waits up to this long for more ready ones          */
+} graver_server_params;
+
+/* One INLP request; every pointer is host memory, read during submit only. */
+typedef struct {
+  int32_t m, n;
+  const int64_t* A;      /* m x n */
+  const int64_t* b;      /* m */
+  const int64_t* l;      /* n */
+  const int64_t* u;      /* n */
+  int32_t f_kind;        /* graver_f_kind */
+  int32_t f_degree;
+  const double* Q;       /* n x n (quadratic) */
+  const double* c;       /* n (quadratic) */
+  const double* coef;    /* n x (degree+1) (separable polynomial) */
+  graver_extract_params extract; /* init_mode 0 (starts z = P g) */
+  graver_init_params init;       /* initial-solution search */
+  int64_t max_steps;             /* augmentation cap per start */
+  int32_t lll;                   /* LLL-reduce the basis */
+  const int64_t* x_starts;       /* n_x_starts x n feasible points, may be NULL */
+  int32_t n_x_starts;
+} graver_request;
+
+typedef struct {
+  graver_status status;    /* of the request's solve                          */
+  double f_best;
+  int32_t d;
+  int64_t unique, filtered, feasible_starts, augment_steps;
+  int32_t batch_size;      /* requests in its batched extraction              */
+  int32_t reused_basis;    /* 1 when the basis came from the A-keyed cache     */
+  double t_submit, t_ready, t_admit, t_done; /* seconds on the server's clock  */
+} graver_result;
+
+/* A request server (Section 3.3's MAPE per request) with continuous
+ * batching: host threads compute kernel bases (Lemma 3.1, Theorem 3.2;
+ * cached by A, whose basis every request with that A reuses); requests whose
+ * basis is ready are admitted while their estimated device footprint
+ * (basis, starts and descent state, candidate pool and log, filter and
+ * augmentation buffers) fits in hbm_budget, in arrival order, and join the
+ * next batched extraction of a free GPU worker (graver_extract_batch);
+ * each request then runs the filter, the initial-solution search and the
+ * augmentation on that worker's stream, and its device memory is released.
+ * Several workers keep several batches on the device at once.
+ * Errors of one request are reported in its result. */
+graver_status graver_server_create(graver_server** out, const graver_server_params* params);
+/* Copies the request; *ticket identifies it.  Never blocks on the GPU. */
+graver_status graver_server_submit(graver_server* srv, const graver_request* req, int64_t* ticket);
+/* Blocks until the request is done; x_best (host, n values, may be NULL). */
+graver_status graver_server_wait(graver_server* srv, int64_t ticket, graver_result* result, int64_t* x_best);
+/* Finishes every submitted request, then stops the threads. */
+void graver_server_destroy(graver_server* srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -27,7 +27,8 @@ STATUS = {0: "OK", -1: "E_INVALID", -2: "E_INFEASIBLE_START", -3: "E_NOT_KERNEL"
 EXPORTED = ["graver_ctx_create", "graver_ctx_destroy", "graver_ctx_set_stream", "graver_last_error",
             "graver_status_string", "graver_kernel_basis", "graver_extract", "graver_filter",
             "graver_augment", "graver_init_solutions", "graver_solve", "graver_lift_inequalities",
-            "graver_extract_batch"]
+            "graver_extract_batch", "graver_server_create", "graver_server_submit", "graver_server_wait",
+            "graver_server_destroy"]
 
 
 class GraverError(RuntimeError):
@@ -92,6 +93,29 @@ class BatchStats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class ServerParams(C.Structure):
+    _fields_ = [("device", C.c_int32), ("hbm_budget", C.c_int64), ("max_batch", C.c_int32),
+                ("gpu_workers", C.c_int32), ("host_threads", C.c_int32), ("autotune", C.c_int32),
+                ("use_graph", C.c_int32), ("batch_window_us", C.c_int32)]
+
+
+class RequestC(C.Structure):
+    _fields_ = [("m", C.c_int32), ("n", C.c_int32), ("A", C.c_void_p), ("b", C.c_void_p), ("l", C.c_void_p),
+                ("u", C.c_void_p), ("f_kind", C.c_int32), ("f_degree", C.c_int32), ("Q", C.c_void_p),
+                ("c", C.c_void_p), ("coef", C.c_void_p), ("extract", ExtractParams), ("init", InitParams),
+                ("max_steps", C.c_int64), ("lll", C.c_int32), ("x_starts", C.c_void_p), ("n_x_starts", C.c_int32)]
+
+
+class ResultC(C.Structure):
+    _fields_ = [("status", C.c_int), ("f_best", C.c_double), ("d", C.c_int32), ("unique", C.c_int64),
+                ("filtered", C.c_int64), ("feasible_starts", C.c_int64), ("augment_steps", C.c_int64),
+                ("batch_size", C.c_int32), ("reused_basis", C.c_int32), ("t_submit", C.c_double),
+                ("t_ready", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class SolveParams(C.Structure):
     _fields_ = [("extract", ExtractParams), ("init", InitParams), ("max_steps", C.c_int64),
                 ("lll", C.c_int32), ("x_starts", C.c_void_p), ("n_x_starts", C.c_int32), ("reuse", C.c_int32)]
@@ -147,9 +171,15 @@ def lib():
         L.graver_extract_batch.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                            C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                            C.POINTER(BatchParams), C.POINTER(BatchStats)]
+        L.graver_server_create.argtypes = [C.POINTER(C.c_void_p), C.POINTER(ServerParams)]
+        L.graver_server_submit.argtypes = [C.c_void_p, C.POINTER(RequestC), C.POINTER(C.c_int64)]
+        L.graver_server_wait.argtypes = [C.c_void_p, C.c_int64, C.POINTER(ResultC), C.c_void_p]
+        L.graver_server_destroy.argtypes = [C.c_void_p]
+        L.graver_server_destroy.restype = None
         for name in ("graver_ctx_create", "graver_ctx_set_stream", "graver_kernel_basis",
                      "graver_extract", "graver_filter", "graver_augment", "graver_init_solutions",
-                     "graver_solve", "graver_lift_inequalities", "graver_extract_batch"):
+                     "graver_solve", "graver_lift_inequalities", "graver_extract_batch",
+                     "graver_server_create", "graver_server_submit", "graver_server_wait"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -391,3 +421,54 @@ def extract_batch(ctx: Context, probs, params, states=None, autotune=False, use_
     _check(lib().graver_extract_batch(ctx.h, cnt, C.byref(pcs), C.byref(prm), st_ptrs, kptr, kcap, out,
                                       C.byref(stt), C.byref(bp), C.byref(bs)))
     return [k[: out[i]] for i, k in enumerate(keys)], [stt[i].as_dict() for i in range(cnt)], bs.as_dict()
+
+
+class Server:
+    """graver_server_*: submit host-side requests, wait for results."""
+
+    def __init__(self, device=0, hbm_budget=64 << 30, max_batch=16, gpu_workers=2, host_threads=4,
+                 autotune=False, use_graph=False, batch_window_us=0):
+        lib()
+        h = C.c_void_p()
+        prm = ServerParams(device, hbm_budget, max_batch, gpu_workers, host_threads, int(autotune),
+                           int(use_graph), batch_window_us)
+        _check(lib().graver_server_create(C.byref(h), C.byref(prm)))
+        self.h = h
+        self.n = {}
+
+    def submit(self, A, b, l, u, extract: ExtractParams, init: InitParams, Q=None, c=None, coef=None,
+               max_steps=10 ** 6, lll=True, x_starts=None) -> int:
+        a = lambda x, dt: None if x is None else np.ascontiguousarray(x, dtype=dt)
+        A, b, l, u = a(A, np.int64), a(b, np.int64), a(l, np.int64), a(u, np.int64)
+        Q, c, coef = a(Q, np.float64), a(c, np.float64), a(coef, np.float64)
+        xs = a(x_starts, np.int64)
+        m, n = A.shape
+        p = lambda x: None if x is None else x.ctypes.data
+        kind = GRAVER_F_QUADRATIC if coef is None else GRAVER_F_SEPARABLE_POLY
+        deg = 0 if coef is None else coef.shape[1] - 1
+        req = RequestC(m, n, p(A), p(b), p(l), p(u), kind, deg, p(Q), p(c), p(coef), extract, init, max_steps,
+                       int(lll), p(xs), 0 if xs is None else xs.shape[0])
+        t = C.c_int64(0)
+        _check(lib().graver_server_submit(self.h, C.byref(req), C.byref(t)))
+        self.n[t.value] = n
+        return t.value
+
+    def wait(self, ticket):
+        """Returns (result dict, x_best numpy int64 or None)."""
+        res = ResultC()
+        n = self.n.pop(ticket)
+        x = np.zeros(n, np.int64)
+        _check(lib().graver_server_wait(self.h, ticket, C.byref(res), x.ctypes.data))
+        r = res.as_dict()
+        return r, (x if r["status"] == 0 else None)
+
+    def close(self):
+        if self.h:
+            lib().graver_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
