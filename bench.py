@@ -82,17 +82,212 @@ def _cpu_baseline(inst, B, P, T, seconds_target=15.0):
                       f"single thread), {el:.1f} s"}
 
 
+def _bases(insts, lll):
+    """Host kernel bases of many instances on a thread pool (ctypes releases the GIL)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    from paper_2412_13576_amd import graver as G
+    with ThreadPoolExecutor(max_workers=16) as ex:
+        return list(ex.map(lambda it: G.kernel_basis(it[0].A, lll=it[1]), [(i, l) for i, l in zip(insts, lll)]))
+
+
+def _line(metric, value, unit, steps, warmup, ms, dtype, config, **extra):
+    out = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": steps, "warmup": warmup,
+           "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+           "data": "synthetic", "config": config}
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+def bench_precision(args):
+    """The precision comparison: quartic workload (m=50, n=400, d=350),
+    262144 starts x 2000 iterations, binary32 vs bf16 (+10% binary32
+    polish); extraction throughput at full size, recall of the filtered
+    sets against filter(F_fp32 u F_bf16) at 65536 starts."""
+    import torch
+
+    from paper_2412_13576_amd import graver as G
+    from paper_2412_13576_amd import workloads as W
+    inst = W.quartic_instance()
+    B, P = G.kernel_basis(inst.A)
+    ctx = G.Context(0)
+    prob = G.DeviceProblem.from_numpy(inst.A, inst.b, inst.l, inst.u, B, P)
+    N, T = args.starts or 262144, args.iters
+    res = {}
+    for prec in ("fp32", "bf16"):
+        pv = G.GRAVER_FP32 if prec == "fp32" else G.GRAVER_BF16
+        prm = G.extract_params(N, T, precision=pv, init_mode=0, seed=3, polish_iters=T // 10 if prec == "bf16" else 0,
+                               collect=0)
+        G.extract(ctx, prob, G.extract_params(4096, 8, precision=pv, init_mode=0, seed=1, collect=0))
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, st = G.extract(ctx, prob, prm)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        res[prec] = {"descent_ms": st["ms_descent"], "wall_ms": el * 1e3,
+                     "start_iterations_per_s": N * T / el,
+                     "tflops": 4.0 * inst.n * B.shape[1] * N * T / (st["ms_descent"] * 1e-3) / 1e12}
+        print(f"[precision] {prec} descent {st['ms_descent']:.1f} ms", file=sys.stderr, flush=True)
+    # recall at 65536 starts (the full-size sets hold ~1e8 keys of 400 bytes)
+    Nr = min(N, 65536)
+    F = {}
+    for prec in ("fp32", "bf16"):
+        pv = G.GRAVER_FP32 if prec == "fp32" else G.GRAVER_BF16
+        k, st = G.extract(ctx, prob, G.extract_params(Nr, T, precision=pv, init_mode=0, seed=3, pool_capacity=1 << 25,
+                                                      polish_iters=T // 10 if prec == "bf16" else 0))
+        F[prec] = G.filter_minimal(ctx, k)
+        res[prec]["unique_at_recall_size"] = int(k.shape[0])
+        del k
+        print(f"[precision] {prec} filtered {F[prec].shape[0]}", file=sys.stderr, flush=True)
+    ref = G.filter_minimal(ctx, torch.cat([F["fp32"], F["bf16"]]))
+    rv = np.ascontiguousarray(ref.cpu().numpy()).view(np.dtype((np.void, ref.shape[1]))).ravel()
+    for prec in ("fp32", "bf16"):
+        fv = np.ascontiguousarray(F[prec].cpu().numpy()).view(np.dtype((np.void, ref.shape[1]))).ravel()
+        res[prec]["recall"] = float(np.isin(rv, fv).sum() / max(1, rv.size))
+    _line("start-iterations/s of the descent, bf16 vs binary32 (extraction, precision comparison)",
+          res["bf16"]["start_iterations_per_s"], "start-iterations/s", 1, 1, res["bf16"]["wall_ms"], "bf16+f32",
+          {"workload": "quartic_m50_n400: m=50, n=400 (d=350), 4 nonzeros per row in +-1..+-5, separable "
+                       "quartic f, box [-20,20]", "starts": N, "iters": T, "recall_starts": Nr},
+          precision=res, speedup_bf16_over_fp32=res["fp32"]["wall_ms"] / res["bf16"]["wall_ms"],
+          roofline={"bound": "mfma", "kernel": "k_descent_big<2,12>", "achieved": res["fp32"]["tflops"],
+                    "peak": PEAK_FP32_MFMA, "unit": "TFLOP/s", "frac": res["fp32"]["tflops"] / PEAK_FP32_MFMA,
+                    "traffic": None, "note": "binary32 launch; the bf16 launch is reported in precision.bf16"})
+    ctx.close()
+
+
+def bench_batch(args):
+    """Batching: 64 instances, n uniform in [50, 500], m = round(U(0.1, 0.3) n),
+    identity-block law [I | C] (C entries 0 w.p. 0.8 else +-1, +-2), 256 n
+    starts each, 1000 iterations, one batched extraction (autotuned tiles,
+    graph-captured rounds), bf16 vs binary32; against the same instances
+    extracted one call at a time."""
+    import torch
+
+    from paper_2412_13576_amd import graver as G
+    from paper_2412_13576_amd import workloads as W
+    rng = np.random.default_rng(4000)
+    ns = rng.integers(50, 501, size=64)
+    ms = [int(round(rng.uniform(0.1, 0.3) * n)) for n in ns]
+    insts = [W.identity_block_instance(4000 + k, int(n), m) for k, (n, m) in enumerate(zip(ns, ms))]
+    bases = _bases(insts, [False] * len(insts))
+    T = args.iters if args.iters != 2000 else 1000
+    probs = [G.DeviceProblem.from_numpy(it.A, it.b, it.l, it.u, B, P) for it, (B, P) in zip(insts, bases)]
+    Ns = [256 * it.n for it in insts]
+    caps = [int(N * max(8, 6000 // it.n)) for N, it in zip(Ns, insts)]
+    total = sum(Ns) * T
+    ctx = G.Context(0)
+    res = {}
+    for prec in ("fp32", "bf16"):
+        pv = G.GRAVER_FP32 if prec == "fp32" else G.GRAVER_BF16
+        prms = [G.extract_params(N, T, precision=pv, init_mode=0, seed=k, pool_capacity=c,
+                                 polish_iters=T // 10 if prec == "bf16" else 0) for k, (N, c) in enumerate(zip(Ns, caps))]
+        # warmup with every instance at full size and 8 iterations: loads the
+        # code objects and runs the tile-shape trials, which the context keeps
+        G.extract_batch(ctx, probs, [G.extract_params(N, 8, precision=pv, init_mode=0, seed=1, pool_capacity=c)
+                                     for N, c in zip(Ns, caps)], autotune=True, use_graph=True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        keys, stats, bs = G.extract_batch(ctx, probs, prms, autotune=True, use_graph=True)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        res[prec] = {"wall_ms": el * 1e3, "start_iterations_per_s": total / el, "batched_descent_ms": bs["ms_descent"],
+                     "launches": bs["launches"], "graphs": bs["graphs"], "replays": bs["replays"],
+                     "unique": int(sum(s["unique"] for s in stats))}
+        del keys
+        print(f"[batch] {prec} {el * 1e3:.0f} ms", file=sys.stderr, flush=True)
+    # the same binary32 work one instance per call
+    prms = [G.extract_params(N, T, precision=G.GRAVER_FP32, init_mode=0, seed=k, pool_capacity=c)
+            for k, (N, c) in enumerate(zip(Ns, caps))]
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for p, pr, c in zip(probs, prms, caps):
+        G.extract(ctx, p, pr, keys_cap=c)
+    torch.cuda.synchronize()
+    seq = time.perf_counter() - t
+    res["fp32_one_call_per_instance"] = {"wall_ms": seq * 1e3, "start_iterations_per_s": total / seq}
+    _line("start-iterations/s, 64 instances in one batched extraction (bf16)", res["bf16"]["start_iterations_per_s"],
+          "start-iterations/s", 1, 1, res["bf16"]["wall_ms"], "bf16+f32",
+          {"workload": "64 identity-block instances [I|C], n ~ U{50..500}, m = round(U(0.1,0.3) n), "
+                       "C density 0.2 in +-1,+-2, box [-5,5]", "starts": "256 n per instance", "iters": T,
+           "total_start_iterations": total}, batch=res)
+    ctx.close()
+
+
+def bench_serve(args):
+    """Serving: Poisson arrivals at 50 requests/s, n log-uniform in
+    [20, 1000], m = round(0.2 n), identity-block law, quadratic (box [-5,5])
+    or separable quartic objective 50/50, binary32 or bf16 descent 50/50,
+    16 n starts x 500 iterations, 8 initial-solution starts plus the
+    instance's feasible point."""
+    from paper_2412_13576_amd import graver as G
+    from paper_2412_13576_amd import workloads as W
+    R = args.requests
+    rng = np.random.default_rng(5000)
+    ns = np.exp(rng.uniform(np.log(20), np.log(1000), size=R)).astype(int)
+    arrivals = np.cumsum(rng.exponential(1.0 / 50.0, size=R))
+    reqs = []
+    for k, n in enumerate(ns):
+        m = max(1, int(round(0.2 * n)))
+        inst = W.identity_block_instance(5000 + k, int(n), m)
+        N = 16 * int(n)
+        bf = rng.random() < 0.5
+        ex = G.extract_params(N, 500, precision=G.GRAVER_BF16 if bf else G.GRAVER_FP32, init_mode=0, seed=k,
+                              pool_capacity=int(N * max(8, 3000 // int(n))), polish_iters=50 if bf else 0)
+        ini = G.init_params(8, 200, seed=k + 1, lr=0.05)
+        if rng.random() < 0.5:
+            obj = dict(Q=inst.Q, c=inst.c)
+        else:
+            coef = np.zeros((int(n), 5))
+            coef[:, 4] = rng.uniform(0.1, 1.0, int(n))
+            coef[:, 3] = rng.standard_normal(int(n))
+            coef[:, 2] = rng.standard_normal(int(n))
+            obj = dict(coef=coef)
+        reqs.append((inst, ex, ini, obj, N))
+    srv = G.Server(hbm_budget=200 << 30, max_batch=32, gpu_workers=2, host_threads=16, autotune=False,
+                   use_graph=True, batch_window_us=2000)
+    t0 = time.perf_counter()
+    tickets = []
+    for (inst, ex, ini, obj, N), at in zip(reqs, arrivals):
+        dt = at - (time.perf_counter() - t0)
+        if dt > 0:
+            time.sleep(dt)
+        tickets.append(srv.submit(inst.A, inst.b, inst.l, inst.u, ex, ini, lll=inst.n <= 200,
+                                  x_starts=inst.x0[None, :], **obj))
+    results = [srv.wait(t)[0] for t in tickets]
+    el = time.perf_counter() - t0
+    srv.close()
+    ok = [r for r in results if r["status"] == 0]
+    lat = np.array([r["t_done"] - r["t_submit"] for r in ok]) * 1e3
+    queue = np.array([r["t_admit"] - r["t_ready"] for r in ok]) * 1e3
+    prep = np.array([r["t_ready"] - r["t_submit"] for r in ok]) * 1e3
+    iters = sum(N * 500 for (_, _, _, _, N), r in zip(reqs, results) if r["status"] == 0)
+    _line("requests/s at Poisson 50 req/s arrivals (p50/p99 solve latency beside)", len(ok) / el, "requests/s", R, 0,
+          el * 1e3 / R, "f32|bf16",
+          {"workload": "Poisson 50/s, identity-block [I|C] n log-uniform [20,1000], m = round(0.2 n), quadratic or "
+                       "quartic, fp32 or bf16, 16 n starts x 500 iterations", "requests": R},
+          latency_ms={"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                      "max": float(lat.max())},
+          basis_ms={"p50": float(np.percentile(prep, 50)), "p99": float(np.percentile(prep, 99))},
+          queue_ms={"p50": float(np.percentile(queue, 50)), "p99": float(np.percentile(queue, 99))},
+          failed=len(results) - len(ok), start_iterations_per_s=iters / el,
+          mean_batch_size=float(np.mean([r["batch_size"] for r in ok])))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--starts", type=int, default=65536)
+    ap.add_argument("--starts", type=int, default=0, help="starts (default: the configuration's)")
     ap.add_argument("--iters", type=int, default=2000)
     ap.add_argument("--aug-starts", type=int, default=200)
     ap.add_argument("--precision", choices=["fp32", "bf16"], default="fp32")
     ap.add_argument("--polish", type=int, default=200, help="bf16: final iterations in binary32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--config", choices=["qp", "precision", "batch", "serve"], default="qp",
+                    help="qp: the benchmark workload (default); the others measure the precision, "
+                         "batching and serving configurations")
+    ap.add_argument("--requests", type=int, default=300, help="serve: number of requests")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device copy (a kernel of known traffic, for counter scaling)")
     args = ap.parse_args()
@@ -100,6 +295,10 @@ def main():
         print("bench.py runs on one GPU only: the hot path is measured on one MI355X "
               "(multi-GPU sharding is described in DESIGN.md, not run)", file=sys.stderr)
         sys.exit(2)
+
+    if args.config != "qp":
+        {"precision": bench_precision, "batch": bench_batch, "serve": bench_serve}[args.config](args)
+        return
 
     import torch
 
@@ -109,7 +308,7 @@ def main():
     inst = W.qp_instance(2000)
     B, P = G.kernel_basis(inst.A)              # host C++ (Lemma 3.1 + LLL), not timed
     n, d = B.shape
-    N, T, S0 = args.starts, args.iters, args.aug_starts
+    N, T, S0 = args.starts or 65536, args.iters, args.aug_starts
     ctx = G.Context(0)
     prob = G.DeviceProblem.from_numpy(inst.A, inst.b, inst.l, inst.u, B, P)
     obj = G.objective("quadratic", Q=inst.Q, c=inst.c)
