@@ -71,7 +71,7 @@ def _cpu_baseline(inst, B, P, T, seconds_target=15.0):
     from oracle import philox
     from oracle import surrogate as S
 
-    n_sample = 384
+    n_sample = 512
     _, z0 = philox.box_starts(P, inst.l, inst.u, n_sample, seed=99)
     t = time.perf_counter()
     iters = T
@@ -320,7 +320,8 @@ def main():
     def step(seed):
         prec = G.GRAVER_FP32 if args.precision == "fp32" else G.GRAVER_BF16
         prm = G.extract_params(N, T, precision=prec, init_mode=0, seed=seed, pool_capacity=pool_cap,
-                               polish_iters=args.polish if args.precision == "bf16" else 0)
+                               polish_iters=args.polish if args.precision == "bf16" else 0,
+                               any_order=True)  # the filter sorts
         keys, st = G.extract(ctx, prob, prm, keys_cap=keys_buf_cap)
         F = G.filter_minimal(ctx, keys)
         x, f, steps, best = G.augment(ctx, prob, obj, F, starts)

@@ -91,6 +91,9 @@ typedef struct {
   uint64_t seed;     /* Philox key for init_mode 0                           */
   int64_t first_start; /* Philox counter offset of start 0 (init_mode 0)     */
   int64_t pool_capacity; /* maximum number of distinct candidates (>= 1)     */
+  int32_t any_order; /* 0: keys sorted lexicographically (deterministic order);
+                        1: keys in the pool's order (the same set; for callers
+                        that filter next, which sorts anyway)               */
 } graver_extract_params;
 
 /* Optional descent state, device pointers to N x d binary64 arrays.  With

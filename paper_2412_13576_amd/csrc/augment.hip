@@ -131,21 +131,50 @@ __global__ void k_eval(AugArgs a, const int64_t* X, const uint32_t* done, const 
   const int s0 = blockIdx.y * kStartGroup;
   const int8_t* g = a.dirs + (size_t)(k < a.K ? k : 0) * n;
   __shared__ Move sh[kStartGroup][kEvalThreads / 64];
+  // slacks of the group's starts, clamped to 127: x_i + g_i stays in
+  // [l_i, u_i] iff -dn_i <= g_i <= up_i, and |g_i| <= 127 keeps the test exact
+  extern __shared__ int8_t slack[];  // [kStartGroup][2][n]: up, then dn
+  for (int t = threadIdx.x; t < kStartGroup * n; t += blockDim.x) {
+    const int si = t / n, i = t % n, s = s0 + si;
+    int64_t up = 0, dn = 0;
+    if (s < a.S) {
+      const int64_t xi = X[(size_t)s * n + i];
+      up = a.u[i] - xi;
+      dn = xi - a.l[i];
+    }
+    slack[(size_t)si * 2 * n + i] = (int8_t)(up < 127 ? up : 127);
+    slack[(size_t)si * 2 * n + n + i] = (int8_t)(dn < 127 ? dn : 127);
+  }
+  __syncthreads();
+  // lambda = 1 feasibility of +g and -g for every start of the group in one
+  // pass over g: bit 2 si is x + g, bit 2 si + 1 is x - g; the pass stops
+  // when no (start, sign) is left (a direction infeasible at lambda = 1 is
+  // infeasible for every lambda)
+  uint32_t fmask = 0;
+  bool any = false;
+  if (k < a.K) {
+    for (int si = 0; si < kStartGroup; ++si) {
+      const int s = s0 + si;
+      if (s < a.S && !done[s]) fmask |= 3u << (2 * si);
+    }
+    for (int i = 0; i < n && fmask; ++i) {
+      const int gi = g[i];
+      if (gi == 0) continue;
+      any = true;
+#pragma unroll
+      for (int si = 0; si < kStartGroup; ++si) {
+        const int up = slack[(size_t)si * 2 * n + i], dn = slack[(size_t)si * 2 * n + n + i];
+        const uint32_t ok = ((gi <= up && -gi <= dn) ? 1u : 0u) | ((-gi <= up && gi <= dn) ? 2u : 0u);
+        fmask &= ~((3u & ~ok) << (2 * si));
+      }
+    }
+  }
   for (int si = 0; si < kStartGroup; ++si) {
     const int s = s0 + si;
     Move best{INFINITY, 0xFFFFFFFFu, 0};
+    const bool fp = (fmask >> (2 * si)) & 1u, fn = (fmask >> (2 * si + 1)) & 1u;
     if (s < a.S && !done[s] && k < a.K) {
       const int64_t* x = X + (size_t)s * n;
-      bool fp = true, fn = true, any = false;
-      for (int i = 0; i < n; ++i) {
-        const int gi = g[i];
-        if (gi == 0) continue;
-        any = true;
-        const int64_t xi = x[i], li = a.l[i], ui = a.u[i];
-        fp = fp && xi + gi >= li && xi + gi <= ui;
-        fn = fn && xi - gi >= li && xi - gi <= ui;
-        if (!fp && !fn) break;
-      }
       if (any && (fp || fn)) {
         int64_t lp = INT64_MAX, ln = INT64_MAX;
         for (int i = 0; i < n; ++i) {
@@ -358,7 +387,8 @@ graver_status run_augment(graver_ctx* ctx, const AugArgs& a, const int64_t* x_st
     for (int64_t step = 0;; ++step) {
       hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, active, (size_t)1);
       hipLaunchKernelGGL(k_prepare, dim3((n + 127) / 128, S), dim3(128), 0, s, a, x_out, done, tab, w, R);
-      hipLaunchKernelGGL(k_eval, dim3(nblk, (S + kStartGroup - 1) / kStartGroup), dim3(kEvalThreads), 0, s, a,
+      hipLaunchKernelGGL(k_eval, dim3(nblk, (S + kStartGroup - 1) / kStartGroup), dim3(kEvalThreads),
+                         (size_t)kStartGroup * 2 * n, s, a,
                          x_out, done, R, qg, qflag, tab, w, partial);
       hipLaunchKernelGGL(k_pick, dim3(S), dim3(256), 0, s, a, nblk, partial, x_out, done, steps_out, active);
       uint32_t hact = 0;

@@ -483,12 +483,18 @@ graver_status job_finish(graver_ctx* ctx, Job& j, int64_t* count_out) {
   }
   {
     EventTimer tm(s);
-    uint32_t p2 = 1024;
-    while (p2 < count) p2 <<= 1;
-    uint32_t* idx = (uint32_t*)W(ctx, j, WS_SORT_IDX, (size_t)p2 * sizeof(uint32_t), &st);
-    if (!idx) return st;
-    HIP_TRY(launch_sort_keys(s, j.pool.keys, j.pool.stride, j.n, count, idx, nullptr, 0, nullptr), "sort");
-    HIP_TRY(launch_gather_keys(s, j.pool.keys, j.pool.stride, j.n, idx, count, j.keys_out, j.n), "gather");
+    if (j.prm->any_order) {
+      if (count)
+        HIP_TRY(hipMemcpy2DAsync(j.keys_out, j.n, j.pool.keys, j.pool.stride, j.n, count, hipMemcpyDeviceToDevice, s),
+                "copy keys");
+    } else {
+      uint32_t p2 = 1024;
+      while (p2 < count) p2 <<= 1;
+      uint32_t* idx = (uint32_t*)W(ctx, j, WS_SORT_IDX, (size_t)p2 * sizeof(uint32_t), &st);
+      if (!idx) return st;
+      HIP_TRY(launch_sort_keys(s, j.pool.keys, j.pool.stride, j.n, count, idx, nullptr, 0, nullptr), "sort");
+      HIP_TRY(launch_gather_keys(s, j.pool.keys, j.pool.stride, j.n, idx, count, j.keys_out, j.n), "gather");
+    }
     j.stt.ms_sort = tm.stop_ms();
   }
   *count_out = count;

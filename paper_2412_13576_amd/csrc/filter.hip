@@ -115,6 +115,105 @@ __global__ void k_compact_rows(const int8_t* src, int stride, const uint32_t* id
   for (int w = 0; w < stride / 8; ++w) b[w] = a[w];
 }
 
+// ---- LSD radix sort of 64-bit keys, 4 bits per pass ----------------------
+// A block owns a tile of kRadixTile consecutive elements, taken in rounds of
+// 256 in element order; the rank of an element among equal digits of its
+// round comes from wave ballots, so every pass is stable.
+constexpr uint32_t kRadixTile = 2048;
+
+__global__ void k_radix_hist(const uint64_t* keys, uint32_t n, int shift, uint32_t nblocks, uint32_t* hist) {
+  __shared__ uint32_t c[16];
+  if (threadIdx.x < 16) c[threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t base = blockIdx.x * kRadixTile;
+  for (uint32_t r = 0; r < kRadixTile / 256; ++r) {
+    const uint32_t e = base + r * 256 + threadIdx.x;
+    if (e < n) atomicAdd(&c[(keys[e] >> shift) & 15], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x < 16) hist[threadIdx.x * nblocks + blockIdx.x] = c[threadIdx.x];
+}
+
+__global__ void k_radix_scatter(const uint64_t* keys, uint64_t* out, uint32_t n, int shift, uint32_t nblocks,
+                                const uint32_t* off) {
+  __shared__ uint32_t wc[4][16];
+  __shared__ uint32_t run[16];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (threadIdx.x < 16) run[threadIdx.x] = off[threadIdx.x * nblocks + blockIdx.x];
+  const uint64_t lt = (1ull << lane) - 1ull;
+  const uint32_t base = blockIdx.x * kRadixTile;
+  for (uint32_t r = 0; r < kRadixTile / 256; ++r) {
+    const uint32_t e = base + r * 256 + threadIdx.x;
+    const bool valid = e < n;
+    const uint64_t k = valid ? keys[e] : 0ull;
+    const int d = valid ? (int)((k >> shift) & 15) : 16;
+    uint32_t rank = 0;
+    for (int v = 0; v < 16; ++v) {
+      const uint64_t m = __ballot(d == v);
+      if (lane == 0) wc[wid][v] = (uint32_t)__popcll(m);
+      if (d == v) rank = (uint32_t)__popcll(m & lt);
+    }
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = run[d] + rank;
+      for (int w = 0; w < wid; ++w) pos += wc[w][d];
+      out[pos] = k;
+    }
+    __syncthreads();
+    if (threadIdx.x < 16) run[threadIdx.x] += wc[0][threadIdx.x] + wc[1][threadIdx.x] + wc[2][threadIdx.x] + wc[3][threadIdx.x];
+    __syncthreads();
+  }
+}
+
+__global__ void k_l1_keys(const int32_t* l1, uint32_t count, int bits_pos, uint64_t* keys) {
+  uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < count) keys[k] = ((uint64_t)(uint32_t)l1[k] << bits_pos) | k;
+}
+
+__global__ void k_low_bits(const uint64_t* keys, uint32_t count, int bits_pos, uint32_t* idx) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) idx[i] = (uint32_t)(keys[i] & ((1ull << bits_pos) - 1ull));
+}
+
+__global__ void k_scatter_flags(const uint32_t* idx, const uint32_t* alive, uint32_t count, uint32_t* flag_lex) {
+  uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < count) flag_lex[idx[p]] = alive[p];
+}
+
+// rows with flag set, in order, into out (n bytes per row); one thread per
+// 4-byte word of a row, so consecutive threads touch consecutive bytes
+__global__ void k_compact_out(const int8_t* src, int stride, const uint32_t* flag, const uint32_t* pos,
+                              uint32_t count, int n, int8_t* out) {
+  const int nw = (n + 3) / 4;
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t i = t / nw;
+  const int w = (int)(t % nw);
+  if (i >= count || !flag[i]) return;
+  const int8_t* a = src + (size_t)i * stride + 4 * w;
+  int8_t* b = out + (size_t)pos[i] * n + 4 * w;
+  if ((n & 3) == 0) {
+    *reinterpret_cast<uint32_t*>(b) = *reinterpret_cast<const uint32_t*>(a);
+  } else {
+    for (int j = 0; j < 4 && 4 * w + j < n; ++j) b[j] = a[j];
+  }
+}
+
+// Sorts keys[0..n) by bits [0, nbits); tmp is scratch of n entries; returns
+// the buffer that holds the result.
+static uint64_t* radix_sort_u64(hipStream_t s, uint64_t* keys, uint64_t* tmp, uint32_t n, int nbits, uint32_t* hist,
+                                uint32_t* off, uint32_t* scratch) {
+  const uint32_t nblocks = (n + kRadixTile - 1) / kRadixTile;
+  for (int shift = 0; shift < nbits; shift += 4) {
+    hipLaunchKernelGGL(k_radix_hist, dim3(nblocks), dim3(256), 0, s, keys, n, shift, nblocks, hist);
+    scan_exclusive(s, hist, off, 16 * nblocks, scratch);
+    hipLaunchKernelGGL(k_radix_scatter, dim3(nblocks), dim3(256), 0, s, keys, tmp, n, shift, nblocks, off);
+    uint64_t* t = keys;
+    keys = tmp;
+    tmp = t;
+  }
+  return keys;
+}
+
 // l1 norm and support masks (W words of positive support, then W of negative).
 __global__ void k_prep(const int8_t* keys, int stride, int n, uint32_t count, int W, int32_t* l1,
                        uint64_t* mask) {
@@ -175,6 +274,7 @@ __global__ void k_level_start(const int32_t* l1, uint32_t count, uint32_t* lo) {
 // (z = nonzeros of g on C) and tests only the keys of those buckets.  The
 // result is the same predicate as testing every pair.
 constexpr int kMaxC = 10;
+constexpr int kJoinThreads = 256;
 struct Coords {
   int k;
   int c[kMaxC];
@@ -228,7 +328,6 @@ __global__ void k_bucket_scatter(const uint32_t* code, uint32_t count, const uin
 // g", 0 or the swapped digit for "-h below g") are the same for every g of
 // the block, so they are enumerated once per block and each is streamed
 // through LDS in tiles, every entry compared against every g of the chunk.
-constexpr int kJoinThreads = 256;
 
 __global__ __launch_bounds__(kJoinThreads) void k_pairs_join(const int8_t* keys, int stride, int n, int W,
                                                            const uint64_t* __restrict__ mask,
@@ -334,8 +433,7 @@ hipError_t launch_filter(hipStream_t s, graver_ctx* ctx, int n, const int8_t* in
   uint64_t* msk = (uint64_t*)ws_get(ctx, WS_F_MASK, (size_t)cnt * 4 * W * 8, st);
   uint32_t* lo = (uint32_t*)ws_get(ctx, WS_F_LO, (size_t)cnt * 4, st);
   uint32_t* alive = (uint32_t*)ws_get(ctx, WS_F_ALIVE, (size_t)cnt * 4 + 64, st);
-  int8_t* surv = (int8_t*)ws_get(ctx, WS_F_OUT, (size_t)cnt * stride, st);
-  if (!canon || !idx || !flag || !pos || !scr || !uniq || !l1 || !msk || !lo || !alive || !surv)
+  if (!canon || !idx || !flag || !pos || !scr || !uniq || !l1 || !msk || !lo || !alive)
     return hipSuccess;
   const unsigned b256 = (cnt + 255) / 256;
   hipLaunchKernelGGL(k_canon, dim3(b256), dim3(256), 0, s, in, (int64_t)cnt, n, stride, canon);
@@ -354,7 +452,21 @@ hipError_t launch_filter(hipStream_t s, graver_ctx* ctx, int n, const int8_t* in
   int32_t* l1b = l1 + cnt;
   uint64_t* mskb = msk + (size_t)cnt * 2 * W;
   hipLaunchKernelGGL(k_prep, dim3(u256), dim3(256), 0, s, uniq, stride, n, U, W, l1, msk);
-  launch_sort_keys(s, uniq, stride, n, U, idx, nullptr, 1, l1);
+  // (l1, lex) order: uniq is lexicographic, so sorting the distinct keys
+  // (l1 << bits_pos) | lex position is a stable reorder by l1
+  {
+    int bits_pos = 1;
+    while (bits_pos < 32 && ((uint64_t)1 << bits_pos) < U) ++bits_pos;
+    int bits_l1 = 1;
+    while (((uint64_t)1 << bits_l1) <= (uint64_t)127 * n) ++bits_l1;
+    const uint32_t nblocks = (U + kRadixTile - 1) / kRadixTile;
+    uint64_t* rk = (uint64_t*)ws_get(ctx, WS_R_KEYS, (size_t)U * 16, st);
+    uint32_t* rh = (uint32_t*)ws_get(ctx, WS_R_HIST, (size_t)nblocks * 16 * 4 * 2 + 64, st);
+    if (!rk || !rh) return hipSuccess;
+    hipLaunchKernelGGL(k_l1_keys, dim3(u256), dim3(256), 0, s, l1, U, bits_pos, rk);
+    uint64_t* sorted = radix_sort_u64(s, rk, rk + U, U, bits_l1 + bits_pos, rh, rh + (size_t)nblocks * 16, scr);
+    hipLaunchKernelGGL(k_low_bits, dim3(u256), dim3(256), 0, s, sorted, U, bits_pos, idx);
+  }
   hipLaunchKernelGGL(k_gather_rows, dim3(u256), dim3(256), 0, s, uniq, stride, idx, U, canon, l1, l1b,
                      msk, mskb, W);
   hipLaunchKernelGGL(k_level_start, dim3(u256), dim3(256), 0, s, l1b, U, lo);
@@ -410,21 +522,22 @@ hipError_t launch_filter(hipStream_t s, graver_ctx* ctx, int n, const int8_t* in
   const unsigned jgrid = ncode < 65535u ? ncode : 65535u;
   hipLaunchKernelGGL(k_pairs_join, dim3(jgrid), dim3(kJoinThreads), jshm, s, canon, stride, n, W, mskb, lo, boff, bl,
                      C, ncode, tile_n, alive);
-  scan_exclusive(s, alive, pos, U, scr);
+  // survivors back in lexicographic order: flags to lex positions, then compact uniq
+  hipLaunchKernelGGL(k_scatter_flags, dim3(u256), dim3(256), 0, s, idx, alive, U, flag);
+  scan_exclusive(s, flag, pos, U, scr);
   hipMemcpyAsync(&hlast[0], pos + U - 1, 4, hipMemcpyDeviceToHost, s);
-  hipMemcpyAsync(&hlast[1], alive + U - 1, 4, hipMemcpyDeviceToHost, s);
+  hipMemcpyAsync(&hlast[1], flag + U - 1, 4, hipMemcpyDeviceToHost, s);
   e = hipStreamSynchronize(s);
   if (e != hipSuccess) return e;
   const uint32_t R = hlast[0] + hlast[1];
-  hipLaunchKernelGGL(k_compact_rows, dim3(u256), dim3(256), 0, s, canon, stride, (const uint32_t*)nullptr,
-                     alive, pos, U, surv);
   *count_out = R;
   if ((int64_t)R > cap) {
     *st = set_error(GRAVER_E_CAPACITY, "keys_cap too small for the filtered set");
     return hipSuccess;
   }
-  launch_sort_keys(s, surv, stride, n, R, idx, nullptr, 0, nullptr);
-  launch_gather_keys(s, surv, stride, n, idx, R, out, n);
+  const uint64_t words = (uint64_t)U * ((n + 3) / 4);
+  hipLaunchKernelGGL(k_compact_out, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, s, uniq, stride, flag, pos,
+                     U, n, out);
   return hipStreamSynchronize(s);
 }
 

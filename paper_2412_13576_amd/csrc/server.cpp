@@ -340,6 +340,7 @@ void gpu_worker(graver_server* s) {
         for (int i = 0; i < k; ++i) {
           probs[i] = live[i].prob;
           prms[i] = batch[i]->ex;
+          prms[i].any_order = 1;  // the filter sorts
           kout[i] = live[i].keys;
           kcap[i] = batch[i]->ex.pool_capacity;
         }
@@ -355,7 +356,9 @@ void gpu_worker(graver_server* s) {
             L.count = cnt[i];
             L.est = est[i];
           } else {
-            st = graver_extract(ctx, &L.prob, &r.ex, nullptr, L.keys, r.ex.pool_capacity, &L.count, &L.est);
+            graver_extract_params ex = r.ex;
+            ex.any_order = 1;
+            st = graver_extract(ctx, &L.prob, &ex, nullptr, L.keys, r.ex.pool_capacity, &L.count, &L.est);
           }
           if (st == GRAVER_OK) {
             r.res.unique = L.count;

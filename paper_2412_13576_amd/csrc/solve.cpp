@@ -142,7 +142,9 @@ extern "C" graver_status graver_solve(graver_ctx* ctx, const graver_problem* pro
     if (!keys) return rc;
     int64_t count = 0;
     graver_extract_stats es{};
-    if ((rc = graver_extract(ctx, &p, &prm->extract, nullptr, keys, cap, &count, &es)) != GRAVER_OK) return rc;
+    graver_extract_params ex = prm->extract;
+    ex.any_order = 1;  // the filter sorts
+    if ((rc = graver_extract(ctx, &p, &ex, nullptr, keys, cap, &count, &es)) != GRAVER_OK) return rc;
     st.unique = count;
     st.ms_extract = ms_since(t0);
 

@@ -54,7 +54,7 @@ class ExtractParams(C.Structure):
                 ("lambda1", C.c_double), ("lambda2", C.c_double),
                 ("init_mode", C.c_int32), ("t0", C.c_int32), ("polish_iters", C.c_int32),
                 ("collect", C.c_int32), ("seed", C.c_uint64), ("first_start", C.c_int64),
-                ("pool_capacity", C.c_int64)]
+                ("pool_capacity", C.c_int64), ("any_order", C.c_int32)]
 
 
 class State(C.Structure):
@@ -259,9 +259,9 @@ class DeviceProblem:
 
 def extract_params(n_starts, iters, precision=GRAVER_FP64, init_mode=0, seed=0, t0=0,
                    pool_capacity=1 << 20, collect=1, lr=0.003, beta1=0.9, beta2=0.999, eps=1e-8,
-                   lambda1=0.85, lambda2=1.0, polish_iters=0, first_start=0) -> ExtractParams:
+                   lambda1=0.85, lambda2=1.0, polish_iters=0, first_start=0, any_order=False) -> ExtractParams:
     return ExtractParams(n_starts, iters, precision, lr, beta1, beta2, eps, lambda1, lambda2, init_mode,
-                         t0, polish_iters, collect, seed, first_start, pool_capacity)
+                         t0, polish_iters, collect, seed, first_start, pool_capacity, int(any_order))
 
 
 def extract(ctx: Context, prob: DeviceProblem, params: ExtractParams, state=None, keys_cap=None):

@@ -359,3 +359,17 @@ def test_log_overflow_replay_keeps_every_candidate(G, ctx):
     ks, ss = G.extract(ctx, prob, small, state={"z": _dev(z0)})
     _say("log overflow replay", "unique", kb.shape[0], "events", sb["inbox_events"], "cap", cap)
     assert torch.equal(kb, ks)
+
+
+def test_any_order_is_the_same_set(G, ctx, qp):
+    """any_order skips the sort: the same keys, in the pool's order."""
+    inst, B, P = qp
+    _say("any order")
+    prob = G.DeviceProblem.from_numpy(inst.A, inst.b, inst.l, inst.u, B, P)
+    prm = dict(precision=G.GRAVER_FP32, init_mode=0, seed=5, pool_capacity=1 << 20)
+    ks, s1 = G.extract(ctx, prob, G.extract_params(8192, 300, **prm))
+    ku, s2 = G.extract(ctx, prob, G.extract_params(8192, 300, any_order=True, **prm))
+    a, b = ks.cpu().numpy(), ku.cpu().numpy()
+    assert a.shape == b.shape and s1["unique"] == s2["unique"]
+    order = np.lexsort(b.T[::-1])
+    assert np.array_equal(b[order], a)
