@@ -7,6 +7,7 @@
 //    lambda_ij = d_j mu_ij (Cohen, "A Course in Computational Algebraic
 //    Number Theory", Sec. 2.6);
 //  * the coordinate map P = (B^T B)^{-1} B^T (Section 3.1) in binary64.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -170,50 +171,83 @@ void lll(int n, int d, std::vector<std::vector<int64_t>>& b) {
   }
 }
 
-// P = (B^T B)^{-1} B^T by Cholesky with one step of iterative refinement.
+// P = (B^T B)^{-1} B^T by Cholesky of the exact Gram matrix (binary64) and
+// one step of iterative refinement, solving for all n right-hand sides at
+// once (row-major d x n panels, so the inner loops run along contiguous
+// memory).
 void projector(int n, int d, const std::vector<std::vector<int64_t>>& b, double* P) {
   std::vector<double> G((size_t)d * d), L((size_t)d * d, 0.0);
+  int64_t bmax = 0;
   for (int i = 0; i < d; ++i)
-    for (int j = 0; j < d; ++j) {
-      __int128 s = 0;
-      for (int r = 0; r < n; ++r) s += (__int128)b[i][r] * b[j][r];
-      G[(size_t)i * d + j] = (double)s;
+    for (int r = 0; r < n; ++r) bmax = std::max<int64_t>(bmax, b[i][r] < 0 ? -b[i][r] : b[i][r]);
+  const bool small = bmax < ((int64_t)1 << 20) && (__int128)n * bmax * bmax < ((__int128)1 << 62);
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j <= i; ++j) {
+      double v;
+      if (small) {  // exact in int64
+        int64_t s = 0;
+        const int64_t* bi = b[i].data();
+        const int64_t* bj = b[j].data();
+        for (int r = 0; r < n; ++r) s += bi[r] * bj[r];
+        v = (double)s;
+      } else {
+        __int128 s = 0;
+        for (int r = 0; r < n; ++r) s += (__int128)b[i][r] * b[j][r];
+        v = (double)s;
+      }
+      G[(size_t)i * d + j] = G[(size_t)j * d + i] = v;
     }
   for (int j = 0; j < d; ++j) {
-    long double s = G[(size_t)j * d + j];
-    for (int k = 0; k < j; ++k) s -= (long double)L[(size_t)j * d + k] * L[(size_t)j * d + k];
-    double dj = std::sqrt((double)s);
+    double s = G[(size_t)j * d + j];
+    for (int k = 0; k < j; ++k) s -= L[(size_t)j * d + k] * L[(size_t)j * d + k];
+    const double dj = std::sqrt(s);
     L[(size_t)j * d + j] = dj;
     for (int i = j + 1; i < d; ++i) {
-      long double t = G[(size_t)i * d + j];
-      for (int k = 0; k < j; ++k) t -= (long double)L[(size_t)i * d + k] * L[(size_t)j * d + k];
-      L[(size_t)i * d + j] = (double)(t / dj);
+      double t = G[(size_t)i * d + j];
+      for (int k = 0; k < j; ++k) t -= L[(size_t)i * d + k] * L[(size_t)j * d + k];
+      L[(size_t)i * d + j] = t / dj;
     }
   }
-  auto solve = [&](std::vector<long double>& x) {  // G x = rhs in place
+  // X (d x n) = G^{-1} R for a d x n panel R, in place
+  auto solve = [&](std::vector<double>& X) {
     for (int i = 0; i < d; ++i) {
-      long double s = x[i];
-      for (int k = 0; k < i; ++k) s -= (long double)L[(size_t)i * d + k] * x[k];
-      x[i] = s / L[(size_t)i * d + i];
+      double* xi = &X[(size_t)i * n];
+      for (int k = 0; k < i; ++k) {
+        const double l = L[(size_t)i * d + k];
+        const double* xk = &X[(size_t)k * n];
+        for (int r = 0; r < n; ++r) xi[r] -= l * xk[r];
+      }
+      const double inv = 1.0 / L[(size_t)i * d + i];
+      for (int r = 0; r < n; ++r) xi[r] *= inv;
     }
     for (int i = d - 1; i >= 0; --i) {
-      long double s = x[i];
-      for (int k = i + 1; k < d; ++k) s -= (long double)L[(size_t)k * d + i] * x[k];
-      x[i] = s / L[(size_t)i * d + i];
+      double* xi = &X[(size_t)i * n];
+      for (int k = i + 1; k < d; ++k) {
+        const double l = L[(size_t)k * d + i];
+        const double* xk = &X[(size_t)k * n];
+        for (int r = 0; r < n; ++r) xi[r] -= l * xk[r];
+      }
+      const double inv = 1.0 / L[(size_t)i * d + i];
+      for (int r = 0; r < n; ++r) xi[r] *= inv;
     }
   };
-  std::vector<long double> x(d), res(d);
-  for (int r = 0; r < n; ++r) {
-    for (int i = 0; i < d; ++i) x[i] = (long double)b[i][r];
-    solve(x);
-    for (int i = 0; i < d; ++i) {
-      long double s = (long double)b[i][r];
-      for (int k = 0; k < d; ++k) s -= (long double)G[(size_t)i * d + k] * x[k];
-      res[i] = s;
+  std::vector<double> X((size_t)d * n), E((size_t)d * n);
+  for (int i = 0; i < d; ++i)
+    for (int r = 0; r < n; ++r) X[(size_t)i * n + r] = (double)b[i][r];
+  solve(X);
+  // residual B^T - G X, then the correction
+  for (int i = 0; i < d; ++i) {
+    double* ei = &E[(size_t)i * n];
+    for (int r = 0; r < n; ++r) ei[r] = (double)b[i][r];
+    for (int k = 0; k < d; ++k) {
+      const double gik = G[(size_t)i * d + k];
+      if (gik == 0.0) continue;
+      const double* xk = &X[(size_t)k * n];
+      for (int r = 0; r < n; ++r) ei[r] -= gik * xk[r];
     }
-    solve(res);
-    for (int i = 0; i < d; ++i) P[(size_t)i * n + r] = (double)(x[i] + res[i]);
   }
+  solve(E);
+  for (size_t t = 0; t < (size_t)d * n; ++t) P[t] = X[t] + E[t];
 }
 
 }  // namespace
