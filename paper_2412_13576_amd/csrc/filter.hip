@@ -323,90 +323,165 @@ __global__ void k_bucket_scatter(const uint32_t* code, uint32_t count, const uin
 }
 
 // Witness search as a tiled join over the sign-pattern index: block b owns
-// the keys g of bucket G = b (the positions bl[off[G] .. off[G+1]) ), one g
-// per thread.  The candidate buckets H (digits 0 or G's digit for "h below
-// g", 0 or the swapped digit for "-h below g") are the same for every g of
-// the block, so they are enumerated once per block and each is streamed
-// through LDS in tiles, every entry compared against every g of the chunk.
+// the keys g of bucket G = b (positions bl[off[G] .. off[G+1]) ), one g per
+// thread.  The candidate buckets H (digits 0 or G's digit for "h below g",
+// 0 or the swapped digit for "-h below g") are the same for every g of the
+// block.  The block enumerates them in parallel (2 * 2^z codes for z
+// nonzero digits of G), keeps the non-empty ones in an LDS list with an
+// exclusive prefix of their sizes, and streams the concatenation of their
+// members through LDS in tiles; every member is compared against every g
+// of the chunk.  Only existence of a witness matters, so the order of the
+// list is free.
+constexpr int kMaxList = 2 << kMaxC;
+constexpr uint32_t kPolBit = 0x80000000u;
+
+// Work items of the join: bucket G is cut into ceil(size / kJoinThreads)
+// chunks of consecutive members; owner[w] = bucket of chunk w, and the
+// chunks of G start at item choff[G].
+__global__ void k_chunk_count(const uint32_t* hist, uint32_t ncode, uint32_t* nch) {
+  uint32_t G = blockIdx.x * blockDim.x + threadIdx.x;
+  if (G > ncode) return;
+  nch[G] = G < ncode ? (hist[G] + kJoinThreads - 1) / kJoinThreads : 0u;
+}
+__global__ void k_chunk_owner(const uint32_t* nch, const uint32_t* choff, uint32_t ncode, uint32_t* owner) {
+  uint32_t G = blockIdx.x * blockDim.x + threadIdx.x;
+  if (G >= ncode) return;
+  for (uint32_t c = 0; c < nch[G]; ++c) owner[choff[G] + c] = G;
+}
 
 __global__ __launch_bounds__(kJoinThreads) void k_pairs_join(const int8_t* keys, int stride, int n, int W,
                                                            const uint64_t* __restrict__ mask,
                                                            const uint32_t* __restrict__ lo,
                                                            const uint32_t* __restrict__ off,
-                                                           const uint32_t* __restrict__ bl, Coords C, uint32_t ncode,
+                                                           const uint32_t* __restrict__ bl, Coords C,
+                                                           const uint32_t* __restrict__ choff,
+                                                           const uint32_t* __restrict__ owner, uint32_t ncode,
                                                            int tile_n, uint32_t* alive) {
   extern __shared__ uint64_t smem_join[];
   uint64_t* tmask = smem_join;                                            // tile_n x 2W
-  uint32_t* tpos = reinterpret_cast<uint32_t*>(tmask + (size_t)tile_n * 2 * W);  // tile_n
+  uint32_t* tpos = reinterpret_cast<uint32_t*>(tmask + (size_t)tile_n * 2 * W);  // tile_n: position | polarity
+  __shared__ uint32_t lst_b[kMaxList];       // bl offset of a non-empty candidate bucket | polarity
+  __shared__ uint32_t lst_pre[kMaxList + 1];  // sizes, then their exclusive prefix (total at [L])
+  __shared__ uint32_t lst_n;
+  __shared__ uint32_t wsum[kJoinThreads / 64];
   __shared__ int any_alive;
-  for (uint32_t G = blockIdx.x; G < ncode; G += gridDim.x) {
-    const uint32_t gb = off[G], ge = off[G + 1];
-    if (gb == ge) continue;
-    int cp[kMaxC], cn[kMaxC];
-    int z = 0;
+  const int lane = threadIdx.x & 63;
+  const uint32_t nwork = choff[ncode];
+  for (uint32_t wk = blockIdx.x; wk < nwork; wk += gridDim.x) {
+    const uint32_t G = owner[wk];
+    const uint32_t gb = off[G] + (wk - choff[G]) * kJoinThreads;
+    const uint32_t ge = min(off[G + 1], gb + kJoinThreads);
+    int dg[kMaxC];
     {
       uint32_t rem = G;
-      for (int i = 0; i < C.k; ++i) {
-        int dgt = (int)(rem % 3u);
+#pragma unroll
+      for (int i = 0; i < kMaxC; ++i) {
+        dg[i] = i < C.k ? (int)(rem % 3u) : 0;
         rem /= 3u;
-        if (dgt) {
-          cp[z] = dgt * C.pow3[i];
-          cn[z] = (3 - dgt) * C.pow3[i];
-          ++z;
-        }
       }
     }
+    int z = 0;
+#pragma unroll
+    for (int i = 0; i < kMaxC; ++i) z += dg[i] != 0;
     const uint32_t nsub = 1u << z;
-    for (uint32_t gc = gb; gc < ge; gc += kJoinThreads) {
-      const uint32_t e = gc + threadIdx.x;
+    __syncthreads();  // the previous item's list is no longer read
+    if (threadIdx.x == 0) lst_n = 0;
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < 2 * nsub; j += kJoinThreads) {
+      const uint32_t pol = j >= nsub ? 1u : 0u;
+      const uint32_t sidx = j - pol * nsub;
+      uint32_t code = 0;
+      int bit = 0;
+#pragma unroll
+      for (int i = 0; i < kMaxC; ++i) {
+        if (dg[i]) {
+          if ((sidx >> bit) & 1u) code += (uint32_t)((pol ? 3 - dg[i] : dg[i]) * C.pow3[i]);
+          ++bit;
+        }
+      }
+      const uint32_t hb = off[code], he = off[code + 1];
+      if (he > hb) {
+        const uint32_t slot = atomicAdd(&lst_n, 1u);
+        lst_b[slot] = hb | (pol ? kPolBit : 0u);
+        lst_pre[slot] = he - hb;
+      }
+    }
+    __syncthreads();
+    const uint32_t L = lst_n;
+    // exclusive prefix of the sizes: each thread a contiguous run, then a
+    // scan of the run sums across the block
+    uint32_t total;
+    {
+      const uint32_t per = (L + kJoinThreads - 1) / kJoinThreads;
+      const uint32_t a0 = min(L, threadIdx.x * per), a1 = min(L, a0 + per);
+      uint32_t loc = 0;
+      for (uint32_t i = a0; i < a1; ++i) loc += lst_pre[i];
+      uint32_t v = loc;
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+      }
+      if (lane == 63) wsum[threadIdx.x >> 6] = v;
+      __syncthreads();
+      uint32_t base = 0;
+      for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) base += wsum[w];
+      uint32_t run = base + v - loc;
+      for (uint32_t i = a0; i < a1; ++i) {
+        const uint32_t sz = lst_pre[i];
+        lst_pre[i] = run;
+        run += sz;
+      }
+      if (threadIdx.x == kJoinThreads - 1) lst_pre[L] = base + v;
+      __syncthreads();
+      total = lst_pre[L];
+    }
+    {
+      const uint32_t e = gb + threadIdx.x;
       const bool valid = e < ge;
       const uint32_t p = valid ? bl[e] : 0u;
       const uint32_t my_lo = valid ? lo[p] : 0u;
-      const int8_t* g = keys + (size_t)p * stride;
       const uint64_t* gm = mask + (size_t)p * 2 * W;
-      uint64_t gp0 = valid ? gm[0] : 0ull, gn0 = valid ? gm[W] : 0ull;
+      const uint64_t gp0 = valid ? gm[0] : 0ull, gn0 = valid ? gm[W] : 0ull;
       const bool idle = !valid || my_lo == 0;  // nothing of smaller l1 to test
+      const int8_t* g = keys + (size_t)p * stride;
       bool dead = false;
-      for (int pol = 0; pol < 2; ++pol) {
-        int code = 0;
-        for (uint32_t sidx = 0; sidx < nsub; ++sidx) {
-          if (sidx) {
-            int t = __builtin_ctz(sidx);
-            uint32_t gray = sidx ^ (sidx >> 1);
-            int cv = pol ? cn[t] : cp[t];
-            code += ((gray >> t) & 1u) ? cv : -cv;
+      for (uint32_t t0 = 0; t0 < total; t0 += tile_n) {
+        __syncthreads();
+        if (threadIdx.x == 0) any_alive = 0;
+        __syncthreads();
+        if (!idle && !dead) any_alive = 1;
+        const uint32_t cnt = min((uint32_t)tile_n, total - t0);
+        for (uint32_t t = threadIdx.x; t < cnt; t += kJoinThreads) {
+          const uint32_t q = t0 + t;
+          uint32_t a = 0, b = L - 1;  // last list entry whose prefix is <= q (prefixes strictly increase)
+          while (a < b) {
+            const uint32_t mid = (a + b + 1) / 2;
+            if (lst_pre[mid] <= q) a = mid; else b = mid - 1;
           }
-          const uint32_t hb = off[code], he = off[code + 1];
-          for (uint32_t t0 = hb; t0 < he; t0 += tile_n) {
-            __syncthreads();
-            if (threadIdx.x == 0) any_alive = 0;
-            __syncthreads();
-            if (!idle && !dead) any_alive = 1;
-            const uint32_t cnt = min((uint32_t)tile_n, he - t0);
-            for (uint32_t t = threadIdx.x; t < cnt; t += kJoinThreads) tpos[t] = bl[t0 + t];
-            __syncthreads();
-            if (!any_alive) continue;
-            for (uint32_t t = threadIdx.x; t < cnt * 2 * W; t += kJoinThreads) {
-              uint32_t ent = t / (2 * W), wd = t % (2 * W);
-              tmask[t] = mask[(size_t)tpos[ent] * 2 * W + wd];
-            }
-            __syncthreads();
-            if (idle || dead) continue;
-            for (uint32_t t = 0; t < cnt && !dead; ++t) {
-              const uint32_t h = tpos[t];
-              if (h >= my_lo) continue;
-              const uint64_t* hm = tmask + (size_t)t * 2 * W;
-              uint64_t hp = hm[0], hn = hm[W];
-              bool ok = pol ? ((hp & ~gn0) | (hn & ~gp0)) == 0 : ((hp & ~gp0) | (hn & ~gn0)) == 0;
-              for (int w = 1; w < W && ok; ++w) {
-                hp = hm[w];
-                hn = hm[W + w];
-                const uint64_t gpw = gm[w], gnw = gm[W + w];
-                ok = pol ? ((hp & ~gnw) | (hn & ~gpw)) == 0 : ((hp & ~gpw) | (hn & ~gnw)) == 0;
-              }
-              if (ok && magnitude_below(keys + (size_t)h * stride, g, n)) dead = true;
-            }
+          const uint32_t hb = lst_b[a];
+          const uint32_t h = bl[(hb & ~kPolBit) + (q - lst_pre[a])];
+          tpos[t] = h | (hb & kPolBit);
+          const uint64_t* hm = mask + (size_t)h * 2 * W;
+          for (int w = 0; w < 2 * W; ++w) tmask[(size_t)t * 2 * W + w] = hm[w];
+        }
+        __syncthreads();
+        if (!any_alive) break;
+        if (idle || dead) continue;
+        for (uint32_t t = 0; t < cnt && !dead; ++t) {
+          const uint32_t hv = tpos[t];
+          const uint32_t h = hv & ~kPolBit;
+          if (h >= my_lo) continue;
+          const bool pol = (hv & kPolBit) != 0;
+          const uint64_t* hm = tmask + (size_t)t * 2 * W;
+          uint64_t hp = hm[0], hn = hm[W];
+          bool ok = pol ? ((hp & ~gn0) | (hn & ~gp0)) == 0 : ((hp & ~gp0) | (hn & ~gn0)) == 0;
+          for (int w = 1; w < W && ok; ++w) {
+            hp = hm[w];
+            hn = hm[W + w];
+            const uint64_t gpw = gm[w], gnw = gm[W + w];
+            ok = pol ? ((hp & ~gnw) | (hn & ~gpw)) == 0 : ((hp & ~gpw) | (hn & ~gnw)) == 0;
           }
+          if (ok && magnitude_below(keys + (size_t)h * stride, g, n)) dead = true;
         }
       }
       if (valid) alive[p] = dead ? 0u : 1u;
@@ -517,11 +592,21 @@ hipError_t launch_filter(hipStream_t s, graver_ctx* ctx, int n, const int8_t* in
   hipLaunchKernelGGL(k_codes, dim3(u256), dim3(256), 0, s, canon, stride, U, C, code, hist);
   scan_exclusive(s, hist, boff, ncode + 1, scr2);
   hipLaunchKernelGGL(k_bucket_scatter, dim3(u256), dim3(256), 0, s, code, U, boff, cur, bl);
+  // join work items: chunks of at most kJoinThreads members of one bucket
+  const size_t max_items = (size_t)(U < ncode ? U : ncode) + U / kJoinThreads + 1;
+  uint32_t* chk = (uint32_t*)ws_get(ctx, WS_F_CHUNK, ((size_t)2 * (ncode + 1) + max_items + 64) * 4, st);
+  if (!chk) return hipSuccess;
+  uint32_t* nch = chk;
+  uint32_t* choff = chk + (ncode + 1);
+  uint32_t* owner = chk + 2 * (size_t)(ncode + 1);
+  hipLaunchKernelGGL(k_chunk_count, dim3(c256), dim3(256), 0, s, hist, ncode, nch);
+  scan_exclusive(s, nch, choff, ncode + 1, scr2);
+  hipLaunchKernelGGL(k_chunk_owner, dim3((ncode + 255) / 256), dim3(256), 0, s, nch, choff, ncode, owner);
   const int tile_n = W <= 4 ? 256 : (W <= 16 ? 64 : 16);
   const size_t jshm = (size_t)tile_n * (2 * W * sizeof(uint64_t) + sizeof(uint32_t));
-  const unsigned jgrid = ncode < 65535u ? ncode : 65535u;
+  const unsigned jgrid = (unsigned)(max_items < 65535u ? max_items : 65535u);
   hipLaunchKernelGGL(k_pairs_join, dim3(jgrid), dim3(kJoinThreads), jshm, s, canon, stride, n, W, mskb, lo, boff, bl,
-                     C, ncode, tile_n, alive);
+                     C, choff, owner, ncode, tile_n, alive);
   // survivors back in lexicographic order: flags to lex positions, then compact uniq
   hipLaunchKernelGGL(k_scatter_flags, dim3(u256), dim3(256), 0, s, idx, alive, U, flag);
   scan_exclusive(s, flag, pos, U, scr);

@@ -81,8 +81,8 @@ enum Slot : int {
   WS_Z = 0, WS_M, WS_V, WS_RPREV, WS_SIGN, WS_KEYSCRATCH, WS_G0,
   WS_POOL_KEYS, WS_POOL_TABLE, WS_POOL_COUNT, WS_COUNTERS,
   WS_BF, WS_BC, WS_SORT_IDX, WS_SORT_TMP, WS_FLAGS, WS_SCAN, WS_SCAN2,
-  WS_F_CANON, WS_F_UNIQ, WS_F_L1, WS_F_MASK, WS_F_LO, WS_F_ALIVE, WS_F_OUT,
-  WS_A_R, WS_A_PART, WS_A_DONE, WS_A_QG, WS_A_TAB, WS_A_PX, WS_A_STEPS,
+  WS_F_CANON, WS_F_UNIQ, WS_F_L1, WS_F_MASK, WS_F_LO, WS_F_ALIVE, WS_F_CHUNK,
+  WS_A_R, WS_A_PART, WS_A_DONE, WS_A_QG, WS_A_TAB,
   WS_MF_B, WS_MF_BT, WS_MF_STATE, WS_MISC,
   WS_F_CODE, WS_F_HIST, WS_F_OFF, WS_F_CUR, WS_F_BL, WS_A_QFLAG, WS_LOG, WS_LOG_COUNT, WS_MF_BAK, WS_MISC2,
   WS_I_X, WS_I_M, WS_I_V, WS_I_R, WS_I_G,

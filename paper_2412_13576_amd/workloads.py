@@ -253,3 +253,43 @@ def feasible_walk_starts(x0: np.ndarray, dirs: np.ndarray, l: np.ndarray,
                     x = y
         out[s] = x
     return out
+
+
+def antichain_with_sums(n: int, n_atoms: int, support: int, n_sums: int, seed: int,
+                        mag: int = 3, positive: bool = False) -> tuple:
+    """Key set whose minimal elements are known in closed form.
+
+    Atoms: n_atoms int8 rows with exactly `support` nonzeros (values in
+    +-1..+-mag) on pairwise distinct supports; rows with distinct supports
+    of one size never lie conformally below one another, or below each
+    other's negation.  positive=True makes every atom nonnegative (all
+    keys then share few sign patterns).  Sums: a + b for random atom pairs whose signs agree
+    wherever both are nonzero (a lies conformally below a + b).  The rows
+    are shuffled, about half are negated, and some sums are repeated.
+    Returns (X, atoms): X the int8 key set, atoms its minimal elements.
+    """
+    rng = _rng(seed)
+    sup = set()
+    rows = []
+    while len(rows) < n_atoms:
+        s = tuple(sorted(rng.choice(n, size=support, replace=False).tolist()))
+        if s in sup:
+            continue
+        sup.add(s)
+        r = np.zeros(n, np.int64)
+        sgn = 1 if positive else rng.choice([-1, 1], size=support)
+        r[list(s)] = rng.integers(1, mag + 1, size=support) * sgn
+        rows.append(r)
+    atoms = np.array(rows, dtype=np.int64)
+    sums = []
+    while len(sums) < n_sums:
+        i = rng.integers(0, n_atoms, size=2 * n_sums)
+        j = rng.integers(0, n_atoms, size=2 * n_sums)
+        ok = (i != j) & np.all(atoms[i] * atoms[j] >= 0, axis=1)
+        s = atoms[i[ok]] + atoms[j[ok]]
+        sums.extend(s[: n_sums - len(sums)])
+    S = np.array(sums, dtype=np.int64)
+    X = np.concatenate([atoms, S, S[: n_sums // 10]])
+    X = X[rng.permutation(X.shape[0])]
+    X[rng.random(X.shape[0]) < 0.5] *= -1
+    return X.astype(np.int8), atoms

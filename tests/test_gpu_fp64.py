@@ -190,6 +190,25 @@ def test_filter_bit_exact(G, ctx, name, X):
     assert _rows(got) == want
 
 
+@pytest.mark.parametrize("shape", ["sparse-600k", "dense-one-pattern-60k"])
+def test_filter_closed_form_large(G, ctx, shape):
+    """Large key sets whose minimal elements are known: atoms on distinct
+    supports of one size plus sums of sign-compatible atom pairs; the filter
+    must return exactly the atoms.  The sparse set spreads over the widest
+    sign-pattern index; the dense nonnegative set puts nearly every key in
+    one bucket, which the join splits into many chunks."""
+    if shape == "sparse-600k":
+        X, atoms = W.antichain_with_sums(n=100, n_atoms=3000, support=6, n_sums=600_000, seed=8)
+    else:
+        X, atoms = W.antichain_with_sums(n=100, n_atoms=2000, support=90, n_sums=60_000, seed=9,
+                                         positive=True)
+    _say("filter closed form", shape, X.shape)
+    want = sorted({canonical(a) for a in atoms})
+    got = G.filter_minimal(ctx, torch.tensor(X, device="cuda"))
+    assert got.shape[0] == len(want)
+    assert _rows(got) == want
+
+
 def test_filter_empty(G, ctx):
     got = G.filter_minimal(ctx, torch.zeros((0, 5), dtype=torch.int8, device="cuda"))
     assert got.shape[0] == 0

@@ -99,3 +99,13 @@ def test_golden_tiny_graver_is_consistent():
         A = W.tiny_instance(seed).A
         for g in list(G)[:200]:
             assert tuple(-x for x in g) in G and in_kernel(A, g)
+
+
+def test_filter_closed_form_antichain_plus_conformal_sums():
+    """Atoms on distinct supports of one size form an antichain; a sum of two
+    sign-compatible atoms has the atom below it, so the minimal set is the
+    atoms themselves (one per sign pair)."""
+    from paper_2412_13576_amd.workloads import antichain_with_sums
+    X, atoms = antichain_with_sums(n=12, n_atoms=40, support=3, n_sums=200, seed=3)
+    got = filter_minimal([tuple(int(v) for v in r) for r in X])
+    assert got == sorted({canonical(a) for a in atoms})
