@@ -469,7 +469,8 @@ graver_status job_finish(graver_ctx* ctx, Job& j, int64_t* count_out) {
       HIP_TRY(hipMemcpyAsync(csr + m + 1, j.csr_col.data(), nnz * 4, hipMemcpyHostToDevice, s), "csr");
       HIP_TRY(hipMemcpyAsync(csr + ints, j.csr_val.data(), nnz * 8, hipMemcpyHostToDevice, s), "csr");
     }
-    HIP_TRY(launch_verify(s, j.pool, count, m, csr, csr + m + 1, reinterpret_cast<const int64_t*>(csr + ints), bad),
+    HIP_TRY(launch_verify(s, j.pool, count, m, (int64_t)nnz, csr, csr + m + 1,
+                          reinterpret_cast<const int64_t*>(csr + ints), bad),
             "verify");
     unsigned int hbad = 0;
     HIP_TRY(hipMemcpyAsync(&hbad, bad, sizeof(hbad), hipMemcpyDeviceToHost, s), "verify flag");
@@ -491,8 +492,9 @@ graver_status job_finish(graver_ctx* ctx, Job& j, int64_t* count_out) {
       uint32_t p2 = 1024;
       while (p2 < count) p2 <<= 1;
       uint32_t* idx = (uint32_t*)W(ctx, j, WS_SORT_IDX, (size_t)p2 * sizeof(uint32_t), &st);
-      if (!idx) return st;
-      HIP_TRY(launch_sort_keys(s, j.pool.keys, j.pool.stride, j.n, count, idx, nullptr, 0, nullptr), "sort");
+      uint64_t* pk = (uint64_t*)W(ctx, j, WS_SORT_TMP, (size_t)p2 * sizeof(uint64_t), &st);
+      if (!idx || !pk) return st;
+      HIP_TRY(launch_sort_keys(s, j.pool.keys, j.pool.stride, count, idx, pk), "sort");
       HIP_TRY(launch_gather_keys(s, j.pool.keys, j.pool.stride, j.n, idx, count, j.keys_out, j.n), "gather");
     }
     j.stt.ms_sort = tm.stop_ms();

@@ -25,19 +25,53 @@ __global__ void k_zero32(uint32_t* a, uint32_t n) {
   if (i < n) a[i] = 0;
 }
 
-__global__ void k_canon(const int8_t* in, int64_t count, int n, int stride, int8_t* out) {
-  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= count) return;
-  const int8_t* g = in + (size_t)k * n;
-  int first = 0;
-  for (int i = 0; i < n; ++i)
-    if (g[i] != 0) {
-      first = g[i];
-      break;
+// Tiles of consecutive rows are staged through LDS: the rows of a tile are
+// one contiguous byte range in both layouts (n bytes per row in, stride
+// bytes out), so loads and stores are coalesced and each thread then works
+// on one row inside LDS.  A block has kTileRows threads; a tile holds up to
+// kTileRows rows and at most kTileBytes bytes.
+constexpr int kTileRows = 256;
+constexpr int kTileBytes = 32768;
+inline int tile_rows_for(int stride) {
+  const int r = kTileBytes / stride;
+  return r < 1 ? 1 : (r > kTileRows ? kTileRows : r);
+}
+
+// each key -> the representative of {g, -g} whose first nonzero is positive,
+// written at the padded stride with zero padding
+__global__ __launch_bounds__(kTileRows) void k_canon(const int8_t* in, int64_t count, int n, int stride,
+                                                     int tile_rows, int8_t* out) {
+  extern __shared__ __align__(16) int8_t ctile[];  // tile_rows x stride
+  const int64_t r0 = (int64_t)blockIdx.x * tile_rows;
+  const int rows = (int)min((int64_t)tile_rows, count - r0);
+  const int8_t* src = in + r0 * n;
+  if ((n & 3) == 0 && (reinterpret_cast<uintptr_t>(in) & 3) == 0) {
+    const int words = rows * n / 4;
+    const uint32_t* s32 = reinterpret_cast<const uint32_t*>(src);
+    for (int w = threadIdx.x; w < words; w += blockDim.x) {
+      const int b = 4 * w, r = b / n;
+      *reinterpret_cast<uint32_t*>(ctile + r * stride + (b - r * n)) = s32[w];
     }
-  int8_t* o = out + (size_t)k * stride;
-  for (int i = 0; i < n; ++i) o[i] = first < 0 ? (int8_t)(-g[i]) : g[i];
-  for (int i = n; i < stride; ++i) o[i] = 0;
+  } else {
+    for (int b = threadIdx.x; b < rows * n; b += blockDim.x) {
+      const int r = b / n;
+      ctile[r * stride + (b - r * n)] = src[b];
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < rows) {
+    int8_t* g = ctile + threadIdx.x * stride;
+    int first = 0;
+    for (int i = 0; i < n && first == 0; ++i) first = g[i];
+    if (first < 0)
+      for (int i = 0; i < n; ++i) g[i] = (int8_t)(-g[i]);
+    for (int i = n; i < stride; ++i) g[i] = 0;
+  }
+  __syncthreads();
+  const int words = rows * stride / 8;
+  const uint64_t* t64 = reinterpret_cast<const uint64_t*>(ctile);
+  uint64_t* o64 = reinterpret_cast<uint64_t*>(out + r0 * stride);
+  for (int w = threadIdx.x; w < words; w += blockDim.x) o64[w] = t64[w];
 }
 
 __device__ __forceinline__ bool rows_equal(const int8_t* keys, int stride, uint32_t a, uint32_t b) {
@@ -215,22 +249,28 @@ static uint64_t* radix_sort_u64(hipStream_t s, uint64_t* keys, uint64_t* tmp, ui
 }
 
 // l1 norm and support masks (W words of positive support, then W of negative).
-__global__ void k_prep(const int8_t* keys, int stride, int n, uint32_t count, int W, int32_t* l1,
-                       uint64_t* mask) {
-  uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= count) return;
-  const int8_t* g = keys + (size_t)k * stride;
+// l1 norm and the positive / negative support bit masks of every key
+__global__ __launch_bounds__(kTileRows) void k_prep(const int8_t* keys, int stride, int n, uint32_t count, int W,
+                                                    int tile_rows, int32_t* l1, uint64_t* mask) {
+  extern __shared__ __align__(16) int8_t ptile[];  // tile_rows x stride
+  const uint32_t r0 = blockIdx.x * (uint32_t)tile_rows;
+  const int rows = (int)min((uint32_t)tile_rows, count - r0);
+  const uint64_t* s64 = reinterpret_cast<const uint64_t*>(keys + (size_t)r0 * stride);
+  for (int w = threadIdx.x; w < rows * stride / 8; w += blockDim.x) reinterpret_cast<uint64_t*>(ptile)[w] = s64[w];
+  __syncthreads();
+  if ((int)threadIdx.x >= rows) return;
+  const int8_t* g = ptile + threadIdx.x * stride;
+  const uint32_t k = r0 + threadIdx.x;
   int32_t s = 0;
   uint64_t* mk = mask + (size_t)k * 2 * W;
   for (int w = 0; w < W; ++w) {
     uint64_t p = 0, q = 0;
-    for (int b = 0; b < 64; ++b) {
-      int i = w * 64 + b;
-      if (i >= n) break;
-      int v = g[i];
+    const int hi = min(64, n - w * 64);
+    for (int b = 0; b < hi; ++b) {
+      const int v = g[w * 64 + b];
       s += v < 0 ? -v : v;
-      if (v > 0) p |= 1ull << b;
-      if (v < 0) q |= 1ull << b;
+      p |= (uint64_t)(v > 0) << b;
+      q |= (uint64_t)(v < 0) << b;
     }
     mk[w] = p;
     mk[W + w] = q;
@@ -511,8 +551,12 @@ hipError_t launch_filter(hipStream_t s, graver_ctx* ctx, int n, const int8_t* in
   if (!canon || !idx || !flag || !pos || !scr || !uniq || !l1 || !msk || !lo || !alive)
     return hipSuccess;
   const unsigned b256 = (cnt + 255) / 256;
-  hipLaunchKernelGGL(k_canon, dim3(b256), dim3(256), 0, s, in, (int64_t)cnt, n, stride, canon);
-  launch_sort_keys(s, canon, stride, n, cnt, idx, nullptr, 0, nullptr);
+  const int trows = tile_rows_for(stride);
+  hipLaunchKernelGGL(k_canon, dim3((cnt + trows - 1) / trows), dim3(kTileRows), (size_t)trows * stride, s, in,
+                     (int64_t)cnt, n, stride, trows, canon);
+  uint64_t* spk = (uint64_t*)ws_get(ctx, WS_SORT_TMP, (size_t)p2 * 8, st);
+  if (!spk) return hipSuccess;
+  launch_sort_keys(s, canon, stride, cnt, idx, spk);
   hipLaunchKernelGGL(k_mark_unique, dim3(b256), dim3(256), 0, s, canon, stride, idx, cnt, flag);
   scan_exclusive(s, flag, pos, cnt, scr);
   uint32_t hlast[2] = {0, 0};
@@ -526,7 +570,8 @@ hipError_t launch_filter(hipStream_t s, graver_ctx* ctx, int n, const int8_t* in
   const unsigned u256 = (U + 255) / 256;
   int32_t* l1b = l1 + cnt;
   uint64_t* mskb = msk + (size_t)cnt * 2 * W;
-  hipLaunchKernelGGL(k_prep, dim3(u256), dim3(256), 0, s, uniq, stride, n, U, W, l1, msk);
+  hipLaunchKernelGGL(k_prep, dim3((U + trows - 1) / trows), dim3(kTileRows), (size_t)trows * stride, s, uniq, stride,
+                     n, U, W, trows, l1, msk);
   // (l1, lex) order: uniq is lexicographic, so sorting the distinct keys
   // (l1 << bits_pos) | lex position is a stable reorder by l1
   {

@@ -206,10 +206,10 @@ hipError_t launch_pool_clear(hipStream_t s, PoolDev p);
 // p[0 .. n) = value (a kernel, so it may be captured in a graph)
 hipError_t launch_fill_u64(hipStream_t s, uint64_t* p, uint64_t n, uint64_t value);
 hipError_t launch_log_insert(hipStream_t s, LogDev log, PoolDev pool);
-hipError_t launch_verify(hipStream_t s, PoolDev p, uint32_t count, int m, const int32_t* rp, const int32_t* col,
-                         const int64_t* val, unsigned int* bad);
-hipError_t launch_sort_keys(hipStream_t s, const int8_t* keys, int stride, int n, uint32_t count,
-                            uint32_t* idx, uint32_t* tmp, int by_l1, const int32_t* l1);
+hipError_t launch_verify(hipStream_t s, PoolDev p, uint32_t count, int m, int64_t nnz, const int32_t* rp,
+                         const int32_t* col, const int64_t* val, unsigned int* bad);
+hipError_t launch_sort_keys(hipStream_t s, const int8_t* keys, int stride, uint32_t count, uint32_t* idx,
+                            uint64_t* pk);
 hipError_t launch_gather_keys(hipStream_t s, const int8_t* keys, int stride, int n,
                               const uint32_t* idx, uint32_t count, int8_t* out, int out_stride);
 

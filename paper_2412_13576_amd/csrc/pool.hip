@@ -31,9 +31,23 @@ hipError_t launch_pool_clear(hipStream_t s, PoolDev p) {
   return hipGetLastError();
 }
 
-// Insert the rows of the candidate log into the pool, one thread per row;
-// all-zero rows are unused slots (a candidate is never zero).
-__global__ void k_log_insert(LogDev log, PoolDev pool) {
+// Insert the rows of the candidate log into the pool in two launches.  No
+// key bytes are written while keys are compared, so the comparisons need no
+// cross-workgroup ordering beyond the table word itself (on a multi-die
+// device, acquire/release at device scope would flush and invalidate the
+// per-die caches on every probe).
+//   probe : a thread per log row (all-zero rows are unused slots) probes the
+//           table with relaxed device-scope atomics; an empty slot is claimed
+//           by a compare-and-swap with the entry (tag, kLogRow | row), so the
+//           entry points at the log row itself.  A tag match is compared
+//           against the log row or the pool key it points at, both written
+//           by earlier launches.
+//   commit: a thread per table slot moves every claimed log row into the
+//           pool (indices taken once per wave) and rewrites the entry to
+//           (tag, pool index).
+constexpr uint32_t kLogRow = 0x80000000u;
+
+__global__ void k_log_probe(LogDev log, PoolDev pool) {
   const uint32_t nrows = min(*log.count, log.cap);
   const int nwords = log.stride / 8;
   for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < nrows; r += gridDim.x * blockDim.x) {
@@ -41,7 +55,80 @@ __global__ void k_log_insert(LogDev log, PoolDev pool) {
     bool nz = false;
     for (int w = 0; w < nwords; ++w) nz |= key[w] != 0;
     if (!nz) continue;
-    pool_insert(pool, key, hash_key_words(key, nwords));
+    const uint64_t h = hash_key_words(key, nwords);
+    const uint32_t tag = (uint32_t)(h >> 32) | 0x80000000u;
+    uint64_t slot = h & pool.tmask;
+    bool settled = false;
+    for (int it = 0; it < kMaxProbeIters && !settled; ++it) {
+      uint64_t e = __hip_atomic_load(&pool.table[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (e == 0) {
+        uint64_t expected = 0;
+        const uint64_t mine = ((uint64_t)tag << 32) | kLogRow | r;
+        if (__hip_atomic_compare_exchange_strong(&pool.table[slot], &expected, mine, __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          settled = true;
+          continue;
+        }
+        e = expected;  // the entry another thread just wrote
+      }
+      if ((uint32_t)(e >> 32) == tag) {
+        const uint32_t lo = (uint32_t)e;
+        const uint64_t* other = reinterpret_cast<const uint64_t*>(
+            (lo & kLogRow) ? log.rows + (size_t)(lo & ~kLogRow) * log.stride : pool.keys + (size_t)lo * pool.stride);
+        bool same = true;
+        for (int w = 0; w < nwords && same; ++w) same = other[w] == key[w];
+        if (same) {
+          settled = true;
+          continue;
+        }
+      }
+      slot = (slot + 1) & pool.tmask;
+    }
+    if (!settled) atomicOr(&pool.count[2], 1u);
+  }
+}
+
+// A wave owns kCommitIters * 64 consecutive slots: it counts the claimed
+// entries with ballots, takes that many pool indices with one atomic, then
+// assigns them in slot order.
+constexpr int kCommitIters = 64;
+
+__global__ void k_log_commit(LogDev log, PoolDev pool) {
+  const int nwords = pool.stride / 8;
+  const uint64_t tsize = pool.tmask + 1;
+  const uint32_t lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+  const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+  const uint64_t s0 = wave * 64 * kCommitIters;
+  if (s0 >= tsize) return;
+  uint32_t cnt = 0;
+  for (int i = 0; i < kCommitIters; ++i) {
+    const uint64_t slot = s0 + (uint64_t)i * 64 + lane;
+    const uint64_t e = slot < tsize ? pool.table[slot] : 0ull;
+    cnt += (uint32_t)__popcll(__ballot(e != 0 && ((uint32_t)e & kLogRow) != 0));
+  }
+  if (cnt == 0) return;
+  uint32_t base = 0;
+  if (lane == 0) base = atomicAdd(&pool.count[0], cnt);
+  base = __shfl(base, 0, 64);
+  for (int i = 0; i < kCommitIters; ++i) {
+    const uint64_t slot = s0 + (uint64_t)i * 64 + lane;
+    const uint64_t e = slot < tsize ? pool.table[slot] : 0ull;
+    const bool pending = e != 0 && ((uint32_t)e & kLogRow) != 0;
+    const uint64_t wm = __ballot(pending);
+    if (pending) {
+      const uint32_t idx =
+          base + __builtin_amdgcn_mbcnt_hi((uint32_t)(wm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)wm, 0u));
+      if (idx >= pool.cap) {
+        atomicOr(&pool.count[1], 1u);
+      } else {
+        const uint64_t* src =
+            reinterpret_cast<const uint64_t*>(log.rows + (size_t)((uint32_t)e & ~kLogRow) * log.stride);
+        uint64_t* dst = reinterpret_cast<uint64_t*>(pool.keys + (size_t)idx * pool.stride);
+        for (int w = 0; w < nwords; ++w) dst[w] = src[w];
+        pool.table[slot] = (e & 0xFFFFFFFF00000000ull) | idx;
+      }
+    }
+    base += (uint32_t)__popcll(wm);
   }
 }
 
@@ -49,7 +136,10 @@ hipError_t launch_log_insert(hipStream_t s, LogDev log, PoolDev pool) {
   unsigned blocks = (unsigned)((log.cap + 255) / 256);
   if (blocks > 8192) blocks = 8192;
   if (blocks == 0) blocks = 1;
-  hipLaunchKernelGGL(k_log_insert, dim3(blocks), dim3(256), 0, s, log, pool);
+  hipLaunchKernelGGL(k_log_probe, dim3(blocks), dim3(256), 0, s, log, pool);
+  const uint64_t tsize = pool.tmask + 1;
+  const uint64_t waves = (tsize + 64 * kCommitIters - 1) / (64 * kCommitIters);
+  hipLaunchKernelGGL(k_log_commit, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, log, pool);
   return hipGetLastError();
 }
 
@@ -85,11 +175,44 @@ __global__ void k_verify(const int8_t* keys, int stride, uint32_t count, int m, 
   }
 }
 
-hipError_t launch_verify(hipStream_t s, PoolDev p, uint32_t count, int m, const int32_t* rp, const int32_t* col,
-                         const int64_t* val, unsigned int* bad) {
+// The same check for a small A: a thread per key, the block's keys staged
+// in LDS with coalesced loads; every thread walks the same CSR entries, so
+// their loads are uniform across the wave.
+constexpr int kVerifyRows = 256;  // threads per block and most rows per tile
+constexpr int kVerifyTileBytes = 32768;
+constexpr int64_t kVerifyRowsMaxNnz = 4096;
+__global__ __launch_bounds__(kVerifyRows) void k_verify_rows(const int8_t* keys, int stride, uint32_t count, int m,
+                                                             int tile_rows, const int32_t* __restrict__ rp,
+                                                             const int32_t* __restrict__ col,
+                                                             const int64_t* __restrict__ val, unsigned int* bad) {
+  extern __shared__ __align__(16) int8_t vtile[];  // tile_rows x stride
+  const uint32_t r0 = blockIdx.x * (uint32_t)tile_rows;
+  const int rows = (int)min((uint32_t)tile_rows, count - r0);
+  const uint64_t* s64 = reinterpret_cast<const uint64_t*>(keys + (size_t)r0 * stride);
+  for (int w = threadIdx.x; w < rows * stride / 8; w += blockDim.x) reinterpret_cast<uint64_t*>(vtile)[w] = s64[w];
+  __syncthreads();
+  if ((int)threadIdx.x >= rows) return;
+  const int8_t* g = vtile + threadIdx.x * stride;
+  bool ok = true;
+  for (int i = 0; i < m; ++i) {
+    int64_t acc = 0;
+    for (int q = rp[i]; q < rp[i + 1]; ++q) acc += val[q] * (int64_t)g[col[q]];
+    ok = ok && acc == 0;
+  }
+  if (!ok) atomicAdd(bad, 1u);
+}
+
+hipError_t launch_verify(hipStream_t s, PoolDev p, uint32_t count, int m, int64_t nnz, const int32_t* rp,
+                         const int32_t* col, const int64_t* val, unsigned int* bad) {
   hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, reinterpret_cast<uint64_t*>(bad),
                      (uint64_t)1, (uint64_t)0);
   if (count == 0) return hipGetLastError();
+  if (nnz <= kVerifyRowsMaxNnz) {
+    const int tr = std::max(1, std::min(kVerifyRows, kVerifyTileBytes / p.stride));
+    hipLaunchKernelGGL(k_verify_rows, dim3((count + tr - 1) / tr), dim3(kVerifyRows), (size_t)tr * p.stride, s,
+                       p.keys, p.stride, count, m, tr, rp, col, val, bad);
+    return hipGetLastError();
+  }
   const uint32_t rounds = (count + 3) / 4;
   const unsigned blocks = (unsigned)std::min<uint32_t>(rounds, 8192u);
   hipLaunchKernelGGL(k_verify, dim3(blocks), dim3(256), (size_t)4 * p.stride, s, p.keys, p.stride, count, m, rp,
@@ -97,92 +220,105 @@ hipError_t launch_verify(hipStream_t s, PoolDev p, uint32_t count, int m, const 
   return hipGetLastError();
 }
 
-// Lexicographic order of signed bytes, component 0 first: flipping the sign
-// bit maps int8 order to uint8 order, and reading 8 bytes big-endian turns
-// the byte sequence order into integer order.
-__device__ __forceinline__ int cmp_rows(const int8_t* keys, int stride, uint32_t a, uint32_t b) {
+// Lexicographic sort of key rows (signed bytes, component 0 first) as
+// (prefix, index) pairs.  Flipping the sign bit of each byte maps int8 order
+// to uint8 order, and reading 8 bytes big-endian turns byte-sequence order
+// into integer order, so the prefix (the first 8 bytes read that way) orders
+// rows by their first 8 components.  Only rows whose prefixes tie are read
+// again, from the second word on; remaining ties go to the smaller index, so
+// the order is total and does not depend on the schedule.  Slots past count
+// hold their own index and sort last.
+__device__ __forceinline__ uint64_t order_word(uint64_t x) { return __builtin_bswap64(x ^ 0x8080808080808080ull); }
+
+__device__ __forceinline__ bool pair_greater(const int8_t* keys, int stride, uint32_t count, uint64_t pa,
+                                             uint32_t a, uint64_t pb, uint32_t b) {
+  const bool va = a < count, vb = b < count;
+  if (!va || !vb) return !va && (vb || a > b);
+  if (pa != pb) return pa > pb;
   const uint64_t* ka = reinterpret_cast<const uint64_t*>(keys + (size_t)a * stride);
   const uint64_t* kb = reinterpret_cast<const uint64_t*>(keys + (size_t)b * stride);
-  for (int w = 0; w < stride / 8; ++w) {
-    uint64_t x = ka[w], y = kb[w];
-    if (x != y) {
-      x = __builtin_bswap64(x ^ 0x8080808080808080ull);
-      y = __builtin_bswap64(y ^ 0x8080808080808080ull);
-      return x < y ? -1 : 1;
-    }
+  for (int w = 1; w < stride / 8; ++w) {
+    const uint64_t x = ka[w], y = kb[w];
+    if (x != y) return order_word(x) > order_word(y);
   }
-  return 0;
+  return a > b;
 }
 
-__device__ __forceinline__ bool row_greater(const int8_t* keys, int stride, uint32_t count,
-                                            int by_l1, const int32_t* l1, uint32_t a, uint32_t b) {
-  if (a >= count || b >= count) return a >= count && (b < count || a > b);
-  if (by_l1 && l1[a] != l1[b]) return l1[a] > l1[b];
-  int c = cmp_rows(keys, stride, a, b);
-  return c != 0 ? c > 0 : a > b;
-}
-
-__global__ void k_bitonic_pass(uint32_t* idx, uint32_t p2, uint32_t k, uint32_t j, const int8_t* keys,
-                               int stride, uint32_t count, int by_l1, const int32_t* l1) {
-  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_sort_init(const int8_t* keys, int stride, uint32_t count, uint32_t p2, uint64_t* pk,
+                            uint32_t* pi) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= p2) return;
-  uint32_t partner = i ^ j;
-  if (partner <= i) return;
-  bool ascending = (i & k) == 0;
-  uint32_t a = idx[i], b = idx[partner];
-  if (row_greater(keys, stride, count, by_l1, l1, a, b) == ascending) {
-    idx[i] = b;
-    idx[partner] = a;
+  pi[i] = i;
+  pk[i] = i < count ? order_word(*reinterpret_cast<const uint64_t*>(keys + (size_t)i * stride)) : ~0ull;
+}
+
+// one bitonic stage (k, j) with j >= 1024: thread = comparator
+__global__ void k_bitonic_pass(uint64_t* pk, uint32_t* pi, uint32_t p2, uint32_t k, uint32_t j, const int8_t* keys,
+                               int stride, uint32_t count) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= p2 / 2) return;
+  const uint32_t lo = (t / j) * 2 * j + (t % j), hi = lo + j;
+  const bool ascending = (lo & k) == 0;
+  const uint64_t pa = pk[lo], pb = pk[hi];
+  const uint32_t a = pi[lo], b = pi[hi];
+  if (pair_greater(keys, stride, count, pa, a, pb, b) == ascending) {
+    pk[lo] = pb;
+    pk[hi] = pa;
+    pi[lo] = b;
+    pi[hi] = a;
   }
 }
 
-// Bitonic passes with j < 2*blockDim run inside one block in LDS.
-__global__ void k_bitonic_local(uint32_t* idx, uint32_t p2, uint32_t k, uint32_t jstart,
-                                const int8_t* keys, int stride, uint32_t count, int by_l1,
-                                const int32_t* l1) {
-  __shared__ uint32_t sh[1024];
-  uint32_t base = blockIdx.x * 1024;
-  for (int t = threadIdx.x; t < 1024; t += blockDim.x) sh[t] = idx[base + t];
+// every stage with j < 1024 of the merge steps k = kmin .. kmax (powers of
+// two), inside 1024-element blocks held in LDS
+__global__ __launch_bounds__(256) void k_bitonic_local(uint64_t* pk, uint32_t* pi, uint32_t kmin, uint32_t kmax,
+                                                       const int8_t* keys, int stride, uint32_t count) {
+  __shared__ uint64_t sk[1024];
+  __shared__ uint32_t si[1024];
+  const uint32_t base = blockIdx.x * 1024;
+  for (int t = threadIdx.x; t < 1024; t += blockDim.x) {
+    sk[t] = pk[base + t];
+    si[t] = pi[base + t];
+  }
   __syncthreads();
-  for (uint32_t j = jstart; j > 0; j >>= 1) {
-    for (int t = threadIdx.x; t < 512; t += blockDim.x) {
-      // t-th comparator of this block: lower element index
-      uint32_t lo = (t / j) * 2 * j + (t % j);
-      uint32_t gi = base + lo;
-      bool ascending = (gi & k) == 0;
-      uint32_t a = sh[lo], b = sh[lo + j];
-      if (row_greater(keys, stride, count, by_l1, l1, a, b) == ascending) {
-        sh[lo] = b;
-        sh[lo + j] = a;
+  for (uint32_t k = kmin; k <= kmax; k <<= 1) {
+    for (uint32_t j = (k >> 1) < 512 ? (k >> 1) : 512; j > 0; j >>= 1) {
+      for (int t = threadIdx.x; t < 512; t += blockDim.x) {
+        const uint32_t lo = (t / j) * 2 * j + (t % j), hi = lo + j;
+        const bool ascending = ((base + lo) & k) == 0;
+        const uint64_t pa = sk[lo], pb = sk[hi];
+        const uint32_t a = si[lo], b = si[hi];
+        if (pair_greater(keys, stride, count, pa, a, pb, b) == ascending) {
+          sk[lo] = pb;
+          sk[hi] = pa;
+          si[lo] = b;
+          si[hi] = a;
+        }
       }
+      __syncthreads();
     }
-    __syncthreads();
   }
-  for (int t = threadIdx.x; t < 1024; t += blockDim.x) idx[base + t] = sh[t];
+  for (int t = threadIdx.x; t < 1024; t += blockDim.x) {
+    pk[base + t] = sk[t];
+    pi[base + t] = si[t];
+  }
 }
 
-__global__ void k_iota(uint32_t* idx, uint32_t n) {
-  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) idx[i] = i;
-}
-
-// Sorts row indices 0..count-1 of `keys` (lexicographic; by (l1, lex) when
-// by_l1).  idx must hold the next power of two >= max(count, 1024) entries.
-hipError_t launch_sort_keys(hipStream_t s, const int8_t* keys, int stride, int n, uint32_t count,
-                            uint32_t* idx, uint32_t* tmp, int by_l1, const int32_t* l1) {
-  (void)n;
-  (void)tmp;
+// Sorts row indices 0..count-1 of `keys` lexicographically into idx.  idx
+// and pk (scratch) must hold the next power of two >= max(count, 1024)
+// entries.
+hipError_t launch_sort_keys(hipStream_t s, const int8_t* keys, int stride, uint32_t count, uint32_t* idx,
+                            uint64_t* pk) {
   uint32_t p2 = 1024;
   while (p2 < count) p2 <<= 1;
-  hipLaunchKernelGGL(k_iota, dim3((p2 + 255) / 256), dim3(256), 0, s, idx, p2);
+  hipLaunchKernelGGL(k_sort_init, dim3((p2 + 255) / 256), dim3(256), 0, s, keys, stride, count, p2, pk, idx);
   if (count <= 1) return hipGetLastError();
-  for (uint32_t k = 2; k <= p2; k <<= 1) {
-    uint32_t j = k >> 1;
-    for (; j >= 1024; j >>= 1)
-      hipLaunchKernelGGL(k_bitonic_pass, dim3((p2 + 255) / 256), dim3(256), 0, s, idx, p2, k, j, keys,
-                         stride, count, by_l1, l1);
-    hipLaunchKernelGGL(k_bitonic_local, dim3(p2 / 1024), dim3(256), 0, s, idx, p2, k, j, keys, stride,
-                       count, by_l1, l1);
+  hipLaunchKernelGGL(k_bitonic_local, dim3(p2 / 1024), dim3(256), 0, s, pk, idx, 2u, 1024u, keys, stride, count);
+  for (uint32_t k = 2048; k <= p2; k <<= 1) {
+    for (uint32_t j = k >> 1; j >= 1024; j >>= 1)
+      hipLaunchKernelGGL(k_bitonic_pass, dim3((p2 / 2 + 255) / 256), dim3(256), 0, s, pk, idx, p2, k, j, keys,
+                         stride, count);
+    hipLaunchKernelGGL(k_bitonic_local, dim3(p2 / 1024), dim3(256), 0, s, pk, idx, k, k, keys, stride, count);
   }
   return hipGetLastError();
 }

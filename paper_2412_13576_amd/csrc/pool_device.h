@@ -5,7 +5,9 @@
 // 0xFFFFFFFE when the pool ran out of key storage (the call then fails).
 // Every lane runs its own bounded probe loop; a lane that wins an empty
 // slot finishes the insert in the same loop iteration, so lanes of one
-// wave never wait on each other.
+// wave never wait on each other.  The lanes of a wave that win a slot in
+// the same iteration take consecutive key indices from one counter update
+// (a single atomic per wave instead of one per new key).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -54,14 +56,26 @@ __device__ inline int pool_insert(const PoolDev& P, const uint64_t* key, uint64_
   const uint32_t tag = (uint32_t)(h >> 32) | 0x80000000u;
   const int nwords = P.stride / 8;
   uint64_t slot = h & P.tmask;
+  const uint32_t lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
   for (int it = 0; it < kMaxProbeIters; ++it) {
     uint64_t e = ld_acquire(&P.table[slot]);
+    bool won = false;
     if (e == 0) {
       uint64_t busy = ((uint64_t)tag << 32) | kIdxBusy;
       uint64_t expected = 0;
-      if (__hip_atomic_compare_exchange_strong(&P.table[slot], &expected, busy, __ATOMIC_ACQ_REL,
-                                               __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) {
-        uint32_t idx = atomicAdd(&P.count[0], 1u);
+      won = __hip_atomic_compare_exchange_strong(&P.table[slot], &expected, busy, __ATOMIC_ACQ_REL,
+                                                 __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // the lanes (still probing) that claimed a slot in this iteration
+    const uint64_t wm = __ballot(won);
+    if (wm) {
+      const uint32_t leader = (uint32_t)__builtin_ctzll(wm);
+      uint32_t base = 0;
+      if (lane == leader) base = atomicAdd(&P.count[0], (uint32_t)__popcll(wm));
+      base = __shfl(base, (int)leader, 64);
+      if (won) {
+        const uint32_t idx =
+            base + __builtin_amdgcn_mbcnt_hi((uint32_t)(wm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)wm, 0u));
         if (idx >= P.cap) {
           atomicOr(&P.count[1], 1u);
           __hip_atomic_store(&P.table[slot], ((uint64_t)tag << 32) | kIdxDead, __ATOMIC_RELEASE,
@@ -75,8 +89,8 @@ __device__ inline int pool_insert(const PoolDev& P, const uint64_t* key, uint64_
                            __HIP_MEMORY_SCOPE_AGENT);
         return 1;
       }
-      continue;  // lost the race: look at the same slot again
     }
+    if (e == 0) continue;  // lost the race: look at the same slot again
     if ((uint32_t)(e >> 32) == tag) {
       uint32_t idx = (uint32_t)e;
       if (idx == kIdxBusy) continue;  // being written by another lane: re-read
