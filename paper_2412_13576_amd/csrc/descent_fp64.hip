@@ -75,14 +75,27 @@ __global__ void k_transpose_f64(int n, int64_t N, const double* G, double* X) {
 }
 
 // z[s, i] = sum_j P[i, j] g[s, j], ascending j from 0.0; z row-major N x d.
+// A thread forms kProjCols outputs of its start per pass over g, so g
+// (column-major n x N, coalesced across threads) is read ceil(d / kProjCols)
+// times.
+constexpr int kProjCols = 16;
 __global__ void k_project(int n, int d, int64_t N, const double* __restrict__ P,
                           const double* __restrict__ g, double* z) {
   int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= N) return;
-  for (int i = 0; i < d; ++i) {
-    double acc = 0.0;
-    for (int j = 0; j < n; ++j) acc = acc + P[(size_t)i * n + j] * g[(size_t)j * N + s];
-    z[(size_t)s * d + i] = acc;
+  for (int i0 = 0; i0 < d; i0 += kProjCols) {
+    double acc[kProjCols];
+#pragma unroll
+    for (int t = 0; t < kProjCols; ++t) acc[t] = 0.0;
+    for (int j = 0; j < n; ++j) {
+      const double gj = g[(size_t)j * N + s];
+#pragma unroll
+      for (int t = 0; t < kProjCols; ++t)
+        if (i0 + t < d) acc[t] = acc[t] + P[(size_t)(i0 + t) * n + j] * gj;
+    }
+#pragma unroll
+    for (int t = 0; t < kProjCols; ++t)
+      if (i0 + t < d) z[(size_t)s * d + i0 + t] = acc[t];
   }
 }
 
