@@ -273,6 +273,57 @@ def bench_serve(args):
           mean_batch_size=float(np.mean([r["batch_size"] for r in ok])))
 
 
+def bench_augment(args):
+    """Multi-start augmentation (Algorithm 1 from every start) on the QP
+    workload with a direction set short enough to move interior points: the
+    filtered binary32 extraction from Gaussian coordinate starts (sigma 0.5),
+    then 200 feasible-walk starts.  (With the box-uniform starts of the main
+    benchmark the extracted directions sit at the edge of the box and no
+    start can move.)  Reports (direction, start) evaluations per second."""
+    import torch
+
+    from paper_2412_13576_amd import graver as G
+    from paper_2412_13576_amd import workloads as W
+    inst = W.qp_instance(2000)
+    B, P = G.kernel_basis(inst.A)
+    n, d = B.shape
+    ctx = G.Context(0)
+    prob = G.DeviceProblem.from_numpy(inst.A, inst.b, inst.l, inst.u, B, P)
+    obj = G.objective("quadratic", Q=inst.Q, c=inst.c)
+    N, T = args.starts or 16384, args.iters
+    z0 = torch.tensor(W.gaussian_starts(N, d, 0.5, 5), device="cuda")
+    prm = G.extract_params(N, T, precision=G.GRAVER_FP32, init_mode=1, pool_capacity=1 << 23, any_order=True)
+    keys, _ = G.extract(ctx, prob, prm, state={"z": z0})
+    F = G.filter_minimal(ctx, keys)
+    del keys
+    S0 = args.aug_starts
+    starts = torch.tensor(W.feasible_walk_starts(inst.x0, B.T.copy(), inst.l, inst.u, S0, seed=7, walk_len=32),
+                          device="cuda")
+    print(f"[augment] {F.shape[0]} directions, {S0} starts", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        G.augment(ctx, prob, obj, F, starts)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        x, f, steps, best = G.augment(ctx, prob, obj, F, starts)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t) / args.steps
+    st = steps.cpu().numpy()
+    K = int(F.shape[0])
+    pairs = K * float((st + 1).sum())  # every active start scores every direction once per pass
+    nnz = float((F != 0).sum(dim=1).double().mean().item())
+    f0 = G.augment(ctx, prob, obj, F[:0], starts)[1].cpu().numpy()
+    _line("(direction, start) evaluations/s of the augmentation (Algorithm 1 from every start)", pairs / el,
+          "evaluations/s", args.steps, args.warmup, el * 1e3, "f64",
+          {"workload": "qp_m20_n100 augmentation: directions = filtered binary32 extraction from "
+                       f"{N} Gaussian coordinate starts (sigma 0.5) x {T} iterations; {S0} feasible-walk starts",
+           "directions": K, "aug_starts": S0},
+          mean_nnz_per_direction=nnz, steps_total=int(st.sum()), steps_max=int(st.max()), passes=int(st.max()) + 1,
+          f_start_mean=float(f0.mean()), f_end_mean=float(f.cpu().numpy().mean()), best_f=float(f[best].item()),
+          f64_flop_lower_bound_tflops=2.0 * nnz * pairs / el / 1e12)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -284,7 +335,7 @@ def main():
     ap.add_argument("--precision", choices=["fp32", "bf16"], default="fp32")
     ap.add_argument("--polish", type=int, default=200, help="bf16: final iterations in binary32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--config", choices=["qp", "precision", "batch", "serve"], default="qp",
+    ap.add_argument("--config", choices=["qp", "precision", "batch", "serve", "augment"], default="qp",
                     help="qp: the benchmark workload (default); the others measure the precision, "
                          "batching and serving configurations")
     ap.add_argument("--requests", type=int, default=300, help="serve: number of requests")
@@ -297,7 +348,8 @@ def main():
         sys.exit(2)
 
     if args.config != "qp":
-        {"precision": bench_precision, "batch": bench_batch, "serve": bench_serve}[args.config](args)
+        {"precision": bench_precision, "batch": bench_batch, "serve": bench_serve,
+         "augment": bench_augment}[args.config](args)
         return
 
     import torch
