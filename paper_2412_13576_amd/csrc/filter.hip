@@ -82,14 +82,21 @@ __device__ __forceinline__ bool rows_equal(const int8_t* keys, int stride, uint3
   return true;
 }
 
-__global__ void k_mark_unique(const int8_t* keys, int stride, const uint32_t* idx, uint32_t count,
-                              uint32_t* flag) {
+// flag[i] = 1 when sorted row i is nonzero and differs from row i - 1; pk
+// holds the sorted 8-byte prefixes, so rows are read only on a prefix tie
+// (or when the prefix is that of a zero row)
+__global__ void k_mark_unique(const int8_t* keys, int stride, const uint32_t* idx, const uint64_t* pk,
+                              uint32_t count, uint32_t* flag) {
   uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
-  const uint64_t* k = reinterpret_cast<const uint64_t*>(keys + (size_t)idx[i] * stride);
-  bool nz = false;
-  for (int w = 0; w < stride / 8; ++w) nz |= k[w] != 0;
-  bool first = i == 0 || !rows_equal(keys, stride, idx[i], idx[i - 1]);
+  constexpr uint64_t kZeroPrefix = 0x8080808080808080ull;
+  const uint64_t p = pk[i];
+  bool nz = p != kZeroPrefix;
+  if (!nz) {
+    const uint64_t* k = reinterpret_cast<const uint64_t*>(keys + (size_t)idx[i] * stride);
+    for (int w = 1; w < stride / 8; ++w) nz |= k[w] != 0;
+  }
+  const bool first = i == 0 || p != pk[i - 1] || !rows_equal(keys, stride, idx[i], idx[i - 1]);
   flag[i] = (nz && first) ? 1u : 0u;
 }
 
@@ -140,13 +147,17 @@ static void scan_exclusive(hipStream_t s, const uint32_t* in, uint32_t* out, uin
   hipLaunchKernelGGL(k_scan_add, dim3(blocks), dim3(1024), 0, s, out, bo, n);
 }
 
+// Row movers run a thread per 8-byte word, so the lanes that copy one row
+// read and write whole cache lines.
 __global__ void k_compact_rows(const int8_t* src, int stride, const uint32_t* idx, const uint32_t* flag,
                                const uint32_t* pos, uint32_t count, int8_t* dst) {
-  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int L = stride / 8;
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t i = t / L;
+  const int w = (int)(t - i * L);
   if (i >= count || !flag[i]) return;
-  const uint64_t* a = reinterpret_cast<const uint64_t*>(src + (size_t)(idx ? idx[i] : i) * stride);
-  uint64_t* b = reinterpret_cast<uint64_t*>(dst + (size_t)pos[i] * stride);
-  for (int w = 0; w < stride / 8; ++w) b[w] = a[w];
+  const uint64_t* a = reinterpret_cast<const uint64_t*>(src + (size_t)(idx ? idx[i] : (uint32_t)i) * stride);
+  reinterpret_cast<uint64_t*>(dst + (size_t)pos[i] * stride)[w] = a[w];
 }
 
 // ---- LSD radix sort of 64-bit keys, 4 bits per pass ----------------------
@@ -278,17 +289,19 @@ __global__ __launch_bounds__(kTileRows) void k_prep(const int8_t* keys, int stri
   l1[k] = s;
 }
 
+// dst row i = src row idx[i] with its l1 and masks (2W <= stride / 8 words)
 __global__ void k_gather_rows(const int8_t* src, int stride, const uint32_t* idx, uint32_t count,
                               int8_t* dst, const int32_t* l1src, int32_t* l1dst, const uint64_t* msrc,
                               uint64_t* mdst, int W) {
-  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int L = stride / 8;
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t i = t / L;
+  const int w = (int)(t - i * L);
   if (i >= count) return;
-  uint32_t j = idx[i];
-  const uint64_t* a = reinterpret_cast<const uint64_t*>(src + (size_t)j * stride);
-  uint64_t* b = reinterpret_cast<uint64_t*>(dst + (size_t)i * stride);
-  for (int w = 0; w < stride / 8; ++w) b[w] = a[w];
-  l1dst[i] = l1src[j];
-  for (int w = 0; w < 2 * W; ++w) mdst[(size_t)i * 2 * W + w] = msrc[(size_t)j * 2 * W + w];
+  const uint32_t j = idx[i];
+  reinterpret_cast<uint64_t*>(dst + (size_t)i * stride)[w] = reinterpret_cast<const uint64_t*>(src + (size_t)j * stride)[w];
+  if (w == 0) l1dst[i] = l1src[j];
+  if (w < 2 * W) mdst[(size_t)i * 2 * W + w] = msrc[(size_t)j * 2 * W + w];
 }
 
 // lo[p] = first position whose l1 equals l1[p] (l1 sorted ascending).
@@ -354,6 +367,15 @@ __global__ void k_codes(const int8_t* keys, int stride, uint32_t count, Coords C
   atomicAdd(&hist[cd], 1u);
 }
 
+// masks in bucket order: bmask row e = mask row bl[e] (a thread per word)
+__global__ void k_bucket_masks(const uint32_t* bl, const uint64_t* mask, uint32_t count, int W, uint64_t* bmask) {
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t e = t / (2 * W);
+  const int w = (int)(t - e * 2 * W);
+  if (e >= count) return;
+  bmask[e * 2 * W + w] = mask[(size_t)bl[e] * 2 * W + w];
+}
+
 __global__ void k_bucket_scatter(const uint32_t* code, uint32_t count, const uint32_t* off, uint32_t* cur,
                                  uint32_t* bl) {
   uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -393,7 +415,8 @@ __global__ __launch_bounds__(kJoinThreads) void k_pairs_join(const int8_t* keys,
                                                            const uint64_t* __restrict__ mask,
                                                            const uint32_t* __restrict__ lo,
                                                            const uint32_t* __restrict__ off,
-                                                           const uint32_t* __restrict__ bl, Coords C,
+                                                           const uint32_t* __restrict__ bl,
+                                                           const uint64_t* __restrict__ bmask, Coords C,
                                                            const uint32_t* __restrict__ choff,
                                                            const uint32_t* __restrict__ owner, uint32_t ncode,
                                                            int tile_n, uint32_t* alive) {
@@ -499,9 +522,9 @@ __global__ __launch_bounds__(kJoinThreads) void k_pairs_join(const int8_t* keys,
             if (lst_pre[mid] <= q) a = mid; else b = mid - 1;
           }
           const uint32_t hb = lst_b[a];
-          const uint32_t h = bl[(hb & ~kPolBit) + (q - lst_pre[a])];
-          tpos[t] = h | (hb & kPolBit);
-          const uint64_t* hm = mask + (size_t)h * 2 * W;
+          const uint32_t e = (hb & ~kPolBit) + (q - lst_pre[a]);
+          tpos[t] = bl[e] | (hb & kPolBit);
+          const uint64_t* hm = bmask + (size_t)e * 2 * W;
           for (int w = 0; w < 2 * W; ++w) tmask[(size_t)t * 2 * W + w] = hm[w];
         }
         __syncthreads();
@@ -557,7 +580,7 @@ hipError_t launch_filter(hipStream_t s, graver_ctx* ctx, int n, const int8_t* in
   uint64_t* spk = (uint64_t*)ws_get(ctx, WS_SORT_TMP, (size_t)p2 * 8, st);
   if (!spk) return hipSuccess;
   launch_sort_keys(s, canon, stride, cnt, idx, spk);
-  hipLaunchKernelGGL(k_mark_unique, dim3(b256), dim3(256), 0, s, canon, stride, idx, cnt, flag);
+  hipLaunchKernelGGL(k_mark_unique, dim3(b256), dim3(256), 0, s, canon, stride, idx, spk, cnt, flag);
   scan_exclusive(s, flag, pos, cnt, scr);
   uint32_t hlast[2] = {0, 0};
   hipMemcpyAsync(&hlast[0], pos + cnt - 1, 4, hipMemcpyDeviceToHost, s);
@@ -566,7 +589,9 @@ hipError_t launch_filter(hipStream_t s, graver_ctx* ctx, int n, const int8_t* in
   if (e != hipSuccess) return e;
   const uint32_t U = hlast[0] + hlast[1];
   if (U == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_compact_rows, dim3(b256), dim3(256), 0, s, canon, stride, idx, flag, pos, cnt, uniq);
+  const uint64_t rw = (uint64_t)stride / 8;
+  hipLaunchKernelGGL(k_compact_rows, dim3((unsigned)((cnt * rw + 255) / 256)), dim3(256), 0, s, canon, stride, idx,
+                     flag, pos, cnt, uniq);
   const unsigned u256 = (U + 255) / 256;
   int32_t* l1b = l1 + cnt;
   uint64_t* mskb = msk + (size_t)cnt * 2 * W;
@@ -587,7 +612,8 @@ hipError_t launch_filter(hipStream_t s, graver_ctx* ctx, int n, const int8_t* in
     uint64_t* sorted = radix_sort_u64(s, rk, rk + U, U, bits_l1 + bits_pos, rh, rh + (size_t)nblocks * 16, scr);
     hipLaunchKernelGGL(k_low_bits, dim3(u256), dim3(256), 0, s, sorted, U, bits_pos, idx);
   }
-  hipLaunchKernelGGL(k_gather_rows, dim3(u256), dim3(256), 0, s, uniq, stride, idx, U, canon, l1, l1b,
+  hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)((U * rw + 255) / 256)), dim3(256), 0, s, uniq, stride, idx, U,
+                     canon, l1, l1b,
                      msk, mskb, W);
   hipLaunchKernelGGL(k_level_start, dim3(u256), dim3(256), 0, s, l1b, U, lo);
   // sign-pattern index on the k most frequently nonzero coordinates
@@ -637,6 +663,11 @@ hipError_t launch_filter(hipStream_t s, graver_ctx* ctx, int n, const int8_t* in
   hipLaunchKernelGGL(k_codes, dim3(u256), dim3(256), 0, s, canon, stride, U, C, code, hist);
   scan_exclusive(s, hist, boff, ncode + 1, scr2);
   hipLaunchKernelGGL(k_bucket_scatter, dim3(u256), dim3(256), 0, s, code, U, boff, cur, bl);
+  // the masks in bucket order go to the first half of the mask buffer (its
+  // lexicographic-order masks are no longer read)
+  uint64_t* bmsk = msk;
+  hipLaunchKernelGGL(k_bucket_masks, dim3((unsigned)(((uint64_t)U * 2 * W + 255) / 256)), dim3(256), 0, s, bl, mskb, U,
+                     W, bmsk);
   // join work items: chunks of at most kJoinThreads members of one bucket
   const size_t max_items = (size_t)(U < ncode ? U : ncode) + U / kJoinThreads + 1;
   uint32_t* chk = (uint32_t*)ws_get(ctx, WS_F_CHUNK, ((size_t)2 * (ncode + 1) + max_items + 64) * 4, st);
@@ -651,7 +682,7 @@ hipError_t launch_filter(hipStream_t s, graver_ctx* ctx, int n, const int8_t* in
   const size_t jshm = (size_t)tile_n * (2 * W * sizeof(uint64_t) + sizeof(uint32_t));
   const unsigned jgrid = (unsigned)(max_items < 65535u ? max_items : 65535u);
   hipLaunchKernelGGL(k_pairs_join, dim3(jgrid), dim3(kJoinThreads), jshm, s, canon, stride, n, W, mskb, lo, boff, bl,
-                     C, choff, owner, ncode, tile_n, alive);
+                     bmsk, C, choff, owner, ncode, tile_n, alive);
   // survivors back in lexicographic order: flags to lex positions, then compact uniq
   hipLaunchKernelGGL(k_scatter_flags, dim3(u256), dim3(256), 0, s, idx, alive, U, flag);
   scan_exclusive(s, flag, pos, U, scr);
