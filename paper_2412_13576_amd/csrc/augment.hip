@@ -111,6 +111,8 @@ __device__ double qg_of(const int8_t* g, int n, const double* Q) {
 }
 
 __device__ __forceinline__ void wave_best(Move& b) {
+  // no lane holds a move: every lane already has the empty move
+  if (__ballot(b.pos != 0xFFFFFFFFu) == 0) return;
   for (int o = 32; o > 0; o >>= 1) {
     Move o2;
     o2.delta = __shfl_xor(b.delta, o, 64);
@@ -157,15 +159,26 @@ __global__ void k_eval(AugArgs a, const int64_t* X, const uint32_t* done, const 
       const int s = s0 + si;
       if (s < a.S && !done[s]) fmask |= 3u << (2 * si);
     }
-    for (int i = 0; i < n && fmask; ++i) {
-      const int gi = g[i];
-      if (gi == 0) continue;
-      any = true;
+    // g is read four bytes at a time when its rows are 4-byte aligned
+    const bool words = (n & 3) == 0 && (reinterpret_cast<uintptr_t>(a.dirs) & 3) == 0;
+    for (int i0 = 0; i0 < n && fmask; i0 += 4) {
+      uint32_t quad = 0;
+      if (words) {
+        quad = *reinterpret_cast<const uint32_t*>(g + i0);
+      } else {
+        for (int b = 0; b < 4 && i0 + b < n; ++b) quad |= (uint32_t)(uint8_t)g[i0 + b] << (8 * b);
+      }
+      for (int b = 0; b < 4 && fmask; ++b) {
+        const int gi = (int8_t)(quad >> (8 * b));
+        if (gi == 0) continue;
+        const int i = i0 + b;
+        any = true;
 #pragma unroll
-      for (int si = 0; si < kStartGroup; ++si) {
-        const int up = slack[(size_t)si * 2 * n + i], dn = slack[(size_t)si * 2 * n + n + i];
-        const uint32_t ok = ((gi <= up && -gi <= dn) ? 1u : 0u) | ((-gi <= up && gi <= dn) ? 2u : 0u);
-        fmask &= ~((3u & ~ok) << (2 * si));
+        for (int si = 0; si < kStartGroup; ++si) {
+          const int up = slack[(size_t)si * 2 * n + i], dn = slack[(size_t)si * 2 * n + n + i];
+          const uint32_t ok = ((gi <= up && -gi <= dn) ? 1u : 0u) | ((-gi <= up && gi <= dn) ? 2u : 0u);
+          fmask &= ~((3u & ~ok) << (2 * si));
+        }
       }
     }
   }

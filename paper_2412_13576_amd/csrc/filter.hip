@@ -327,7 +327,7 @@ __global__ void k_level_start(const int32_t* l1, uint32_t count, uint32_t* lo) {
 // (z = nonzeros of g on C) and tests only the keys of those buckets.  The
 // result is the same predicate as testing every pair.
 constexpr int kMaxC = 11;
-constexpr int kJoinThreads = 256;
+constexpr int kJoinThreads = 64;  // one wave
 struct Coords {
   int k;
   int c[kMaxC];
@@ -384,17 +384,18 @@ __global__ void k_bucket_scatter(const uint32_t* code, uint32_t count, const uin
   bl[off[cd] + atomicAdd(&cur[cd], 1u)] = p;
 }
 
-// Witness search as a tiled join over the sign-pattern index: block b owns
-// the keys g of bucket G = b (positions bl[off[G] .. off[G+1]) ), one g per
-// thread.  The candidate buckets H (digits 0 or G's digit for "h below g",
-// 0 or the swapped digit for "-h below g") are the same for every g of the
-// block.  The block enumerates them in parallel (2 * 2^z codes for z
-// nonzero digits of G), keeps the non-empty ones in an LDS list with an
-// exclusive prefix of their sizes, and streams the concatenation of their
-// members through LDS in tiles; every member is compared against every g
-// of the chunk.  Only existence of a witness matters, so the order of the
-// list is free.
-constexpr int kMaxList = 2 << kMaxC;
+// Witness search as a tiled join over the sign-pattern index.  A work item
+// is a chunk of at most kJoinThreads keys g of one bucket G, one g per lane
+// of a one-wave block.  The candidate buckets H (digits 0 or G's digit for
+// "h below g", 0 or the swapped digit for "-h below g") are the same for
+// every g of the item.  The wave enumerates them in rounds of kListCap codes
+// (2 * 2^z codes for z nonzero digits of G), keeps the non-empty ones of a
+// round in an LDS list with an exclusive prefix of their sizes, and streams
+// the concatenation of their members through LDS in tiles; every member is
+// compared against every g of the chunk.  Only existence of a witness
+// matters, so the order of the list is free.
+constexpr int kListCap = 256;
+constexpr int kListPerLane = kListCap / kJoinThreads;
 constexpr uint32_t kPolBit = 0x80000000u;
 
 // Work items of the join: bucket G is cut into ceil(size / kJoinThreads)
@@ -423,12 +424,9 @@ __global__ __launch_bounds__(kJoinThreads) void k_pairs_join(const int8_t* keys,
   extern __shared__ uint64_t smem_join[];
   uint64_t* tmask = smem_join;                                            // tile_n x 2W
   uint32_t* tpos = reinterpret_cast<uint32_t*>(tmask + (size_t)tile_n * 2 * W);  // tile_n: position | polarity
-  __shared__ uint32_t lst_b[kMaxList];       // bl offset of a non-empty candidate bucket | polarity
-  __shared__ uint32_t lst_pre[kMaxList + 1];  // sizes, then their exclusive prefix (total at [L])
-  __shared__ uint32_t lst_n;
-  __shared__ uint32_t wsum[kJoinThreads / 64];
-  __shared__ int any_alive;
-  const int lane = threadIdx.x & 63;
+  __shared__ uint32_t lst_b[kListCap];       // bl offset of a non-empty candidate bucket | polarity
+  __shared__ uint32_t lst_pre[kListCap + 1];  // sizes, then their exclusive prefix (total at [L])
+  const uint32_t lane = threadIdx.x;
   const uint32_t nwork = choff[ncode];
   for (uint32_t wk = blockIdx.x; wk < nwork; wk += gridDim.x) {
     const uint32_t G = owner[wk];
@@ -447,74 +445,76 @@ __global__ __launch_bounds__(kJoinThreads) void k_pairs_join(const int8_t* keys,
 #pragma unroll
     for (int i = 0; i < kMaxC; ++i) z += dg[i] != 0;
     const uint32_t nsub = 1u << z;
-    __syncthreads();  // the previous item's list is no longer read
-    if (threadIdx.x == 0) lst_n = 0;
-    __syncthreads();
-    for (uint32_t j = threadIdx.x; j < 2 * nsub; j += kJoinThreads) {
-      const uint32_t pol = j >= nsub ? 1u : 0u;
-      const uint32_t sidx = j - pol * nsub;
-      uint32_t code = 0;
-      int bit = 0;
+    const uint32_t e = gb + lane;
+    const bool valid = e < ge;
+    const uint32_t p = valid ? bl[e] : 0u;
+    const uint32_t my_lo = valid ? lo[p] : 0u;
+    const uint64_t* gm = mask + (size_t)p * 2 * W;
+    const uint64_t gp0 = valid ? gm[0] : 0ull, gn0 = valid ? gm[W] : 0ull;
+    const bool idle = !valid || my_lo == 0;  // nothing of smaller l1 to test
+    const int8_t* g = keys + (size_t)p * stride;
+    bool dead = false;
+    for (uint32_t j0 = 0; j0 < 2 * nsub; j0 += kListCap) {
+      if (__ballot(!idle && !dead) == 0) break;
+      __syncthreads();  // the previous round's list and tiles are no longer read
+      // non-empty candidate buckets of codes j0 .. j0 + kListCap - 1
+      uint32_t L = 0;
+      for (int r = 0; r < kListPerLane; ++r) {
+        const uint32_t j = j0 + (uint32_t)r * kJoinThreads + lane;
+        uint32_t hb = 0, he = 0, pol = 0;
+        if (j < 2 * nsub) {
+          pol = j >= nsub ? 1u : 0u;
+          const uint32_t sidx = j - pol * nsub;
+          uint32_t code = 0;
+          int bit = 0;
 #pragma unroll
-      for (int i = 0; i < kMaxC; ++i) {
-        if (dg[i]) {
-          if ((sidx >> bit) & 1u) code += (uint32_t)((pol ? 3 - dg[i] : dg[i]) * C.pow3[i]);
-          ++bit;
+          for (int i = 0; i < kMaxC; ++i) {
+            if (dg[i]) {
+              if ((sidx >> bit) & 1u) code += (uint32_t)((pol ? 3 - dg[i] : dg[i]) * C.pow3[i]);
+              ++bit;
+            }
+          }
+          hb = off[code];
+          he = off[code + 1];
         }
+        const bool keep = he > hb;
+        const uint64_t km = __ballot(keep);
+        if (keep) {
+          const uint32_t slot =
+              L + __builtin_amdgcn_mbcnt_hi((uint32_t)(km >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
+          lst_b[slot] = hb | (pol ? kPolBit : 0u);
+          lst_pre[slot] = he - hb;
+        }
+        L += (uint32_t)__popcll(km);
       }
-      const uint32_t hb = off[code], he = off[code + 1];
-      if (he > hb) {
-        const uint32_t slot = atomicAdd(&lst_n, 1u);
-        lst_b[slot] = hb | (pol ? kPolBit : 0u);
-        lst_pre[slot] = he - hb;
-      }
-    }
-    __syncthreads();
-    const uint32_t L = lst_n;
-    // exclusive prefix of the sizes: each thread a contiguous run, then a
-    // scan of the run sums across the block
-    uint32_t total;
-    {
-      const uint32_t per = (L + kJoinThreads - 1) / kJoinThreads;
-      const uint32_t a0 = min(L, threadIdx.x * per), a1 = min(L, a0 + per);
-      uint32_t loc = 0;
-      for (uint32_t i = a0; i < a1; ++i) loc += lst_pre[i];
-      uint32_t v = loc;
-      for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t t = __shfl_up(v, o, 64);
-        if (lane >= o) v += t;
-      }
-      if (lane == 63) wsum[threadIdx.x >> 6] = v;
+      if (L == 0) continue;
       __syncthreads();
-      uint32_t base = 0;
-      for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) base += wsum[w];
-      uint32_t run = base + v - loc;
-      for (uint32_t i = a0; i < a1; ++i) {
-        const uint32_t sz = lst_pre[i];
-        lst_pre[i] = run;
-        run += sz;
+      // exclusive prefix of the sizes: lane t sums entries [t * kListPerLane, ...)
+      uint32_t total;
+      {
+        const uint32_t a0 = min(L, lane * kListPerLane), a1 = min(L, a0 + kListPerLane);
+        uint32_t loc = 0;
+        for (uint32_t i = a0; i < a1; ++i) loc += lst_pre[i];
+        uint32_t v = loc;
+        for (int o = 1; o < kJoinThreads; o <<= 1) {
+          const uint32_t t = __shfl_up(v, o, kJoinThreads);
+          if ((int)lane >= o) v += t;
+        }
+        uint32_t run = v - loc;
+        for (uint32_t i = a0; i < a1; ++i) {
+          const uint32_t sz = lst_pre[i];
+          lst_pre[i] = run;
+          run += sz;
+        }
+        total = __shfl(v, kJoinThreads - 1, kJoinThreads);
+        if (lane == 0) lst_pre[L] = total;
       }
-      if (threadIdx.x == kJoinThreads - 1) lst_pre[L] = base + v;
       __syncthreads();
-      total = lst_pre[L];
-    }
-    {
-      const uint32_t e = gb + threadIdx.x;
-      const bool valid = e < ge;
-      const uint32_t p = valid ? bl[e] : 0u;
-      const uint32_t my_lo = valid ? lo[p] : 0u;
-      const uint64_t* gm = mask + (size_t)p * 2 * W;
-      const uint64_t gp0 = valid ? gm[0] : 0ull, gn0 = valid ? gm[W] : 0ull;
-      const bool idle = !valid || my_lo == 0;  // nothing of smaller l1 to test
-      const int8_t* g = keys + (size_t)p * stride;
-      bool dead = false;
       for (uint32_t t0 = 0; t0 < total; t0 += tile_n) {
-        __syncthreads();
-        if (threadIdx.x == 0) any_alive = 0;
-        __syncthreads();
-        if (!idle && !dead) any_alive = 1;
+        if (__ballot(!idle && !dead) == 0) break;
         const uint32_t cnt = min((uint32_t)tile_n, total - t0);
-        for (uint32_t t = threadIdx.x; t < cnt; t += kJoinThreads) {
+        __syncthreads();  // the previous tile is no longer read
+        for (uint32_t t = lane; t < cnt; t += kJoinThreads) {
           const uint32_t q = t0 + t;
           uint32_t a = 0, b = L - 1;  // last list entry whose prefix is <= q (prefixes strictly increase)
           while (a < b) {
@@ -522,13 +522,12 @@ __global__ __launch_bounds__(kJoinThreads) void k_pairs_join(const int8_t* keys,
             if (lst_pre[mid] <= q) a = mid; else b = mid - 1;
           }
           const uint32_t hb = lst_b[a];
-          const uint32_t e = (hb & ~kPolBit) + (q - lst_pre[a]);
-          tpos[t] = bl[e] | (hb & kPolBit);
-          const uint64_t* hm = bmask + (size_t)e * 2 * W;
+          const uint32_t eb = (hb & ~kPolBit) + (q - lst_pre[a]);
+          tpos[t] = bl[eb] | (hb & kPolBit);
+          const uint64_t* hm = bmask + (size_t)eb * 2 * W;
           for (int w = 0; w < 2 * W; ++w) tmask[(size_t)t * 2 * W + w] = hm[w];
         }
         __syncthreads();
-        if (!any_alive) break;
         if (idle || dead) continue;
         for (uint32_t t = 0; t < cnt && !dead; ++t) {
           const uint32_t hv = tpos[t];
@@ -547,8 +546,8 @@ __global__ __launch_bounds__(kJoinThreads) void k_pairs_join(const int8_t* keys,
           if (ok && magnitude_below(keys + (size_t)h * stride, g, n)) dead = true;
         }
       }
-      if (valid) alive[p] = dead ? 0u : 1u;
     }
+    if (valid) alive[p] = dead ? 0u : 1u;
   }
 }
 
@@ -680,7 +679,7 @@ hipError_t launch_filter(hipStream_t s, graver_ctx* ctx, int n, const int8_t* in
   hipLaunchKernelGGL(k_chunk_owner, dim3((ncode + 255) / 256), dim3(256), 0, s, nch, choff, ncode, owner);
   const int tile_n = W <= 4 ? 256 : (W <= 16 ? 64 : 16);
   const size_t jshm = (size_t)tile_n * (2 * W * sizeof(uint64_t) + sizeof(uint32_t));
-  const unsigned jgrid = (unsigned)(max_items < 65535u ? max_items : 65535u);
+  const unsigned jgrid = (unsigned)(max_items < (1u << 20) ? max_items : (1u << 20));
   hipLaunchKernelGGL(k_pairs_join, dim3(jgrid), dim3(kJoinThreads), jshm, s, canon, stride, n, W, mskb, lo, boff, bl,
                      bmsk, C, choff, owner, ncode, tile_n, alive);
   // survivors back in lexicographic order: flags to lex positions, then compact uniq
