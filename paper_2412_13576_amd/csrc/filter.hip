@@ -326,7 +326,7 @@ __global__ void k_level_start(const int32_t* l1, uint32_t count, uint32_t* lo) {
 // g" digits that are 0 or the swapped digit; g enumerates these 2^z codes
 // (z = nonzeros of g on C) and tests only the keys of those buckets.  The
 // result is the same predicate as testing every pair.
-constexpr int kMaxC = 11;
+constexpr int kMaxC = 12;
 constexpr int kJoinThreads = 64;  // one wave
 struct Coords {
   int k;
@@ -622,7 +622,7 @@ hipError_t launch_filter(hipStream_t s, graver_ctx* ctx, int n, const int8_t* in
     if (U >= 64) {
       int lg = 0;
       while ((1u << (lg + 1)) <= U) ++lg;
-      k = (lg + 1) / 2 + 1;
+      k = (lg + 1) / 2 + 2;
     }
     k = k < kMaxC ? k : kMaxC;
     k = k < n ? k : n;
