@@ -31,17 +31,23 @@ __device__ __forceinline__ bool better(const Move& a, const Move& b) {
   return a.lam < b.lam;
 }
 
+// start feasibility: thread t < S*m checks row t % m of A x = b for start
+// t / m; the next S*n threads check l <= x <= u coordinate by coordinate
 __global__ void k_check_starts(int n, int m, int S, const int64_t* A, const int64_t* b, const int64_t* l,
                                const int64_t* u, const int64_t* X, unsigned int* bad) {
-  int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= S) return;
-  const int64_t* x = X + (size_t)s * n;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t rows = (int64_t)S * m;
   bool ok = true;
-  for (int i = 0; i < n; ++i) ok = ok && x[i] >= l[i] && x[i] <= u[i];
-  for (int r = 0; r < m && ok; ++r) {
+  if (t < rows) {
+    const int s = (int)(t / m), r = (int)(t % m);
+    const int64_t* x = X + (size_t)s * n;
     int64_t acc = 0;
     for (int j = 0; j < n; ++j) acc += A[(size_t)r * n + j] * x[j];
     ok = acc == b[r];
+  } else if (t < rows + (int64_t)S * n) {
+    const int64_t k = t - rows;
+    const int i = (int)(k % n);
+    ok = X[k] >= l[i] && X[k] <= u[i];
   }
   if (!ok) atomicAdd(bad, 1u);
 }
@@ -92,7 +98,7 @@ __global__ void k_prepare(AugArgs a, const int64_t* X, const uint32_t* done, con
 }
 
 constexpr int kEvalThreads = 256;
-constexpr int kStartGroup = 8;
+constexpr int kStartGroup = 16;  // 2 bits per start in a 32-bit feasibility mask
 
 // q_g of one direction (ascending sums over its support), computed the
 // first time some start can move along g and cached for the call.
@@ -365,7 +371,9 @@ graver_status run_augment(graver_ctx* ctx, const AugArgs& a, const int64_t* x_st
   if (!bad || !done || !R || !partial || !qg || !dbest) return st;
 
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, bad, (size_t)16);
-  hipLaunchKernelGGL(k_check_starts, dim3((S + 63) / 64), dim3(64), 0, s, n, a.m, S, a.A, a.b, a.l, a.u,
+  const int64_t checks = (int64_t)S * (a.m + n);
+  hipLaunchKernelGGL(k_check_starts, dim3((unsigned)((checks + 255) / 256)), dim3(256), 0, s, n, a.m, S, a.A, a.b,
+                     a.l, a.u,
                      x_starts, bad);
   unsigned int hbad = 0;
   hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, s);

@@ -342,22 +342,33 @@ __device__ __forceinline__ bool magnitude_below(const int8_t* h, const int8_t* g
   return true;
 }
 
-// nonzero count of every coordinate; block = 1024 rows, thread = column
-__global__ void k_col_nnz(const int8_t* keys, int stride, int n, uint32_t count, uint32_t* cnt) {
-  uint32_t r0 = blockIdx.x * 1024u;
-  uint32_t r1 = min(count, r0 + 1024u);
+// nonzero count of every coordinate over the rows r = i * step, i < rows
+// (they only rank the coordinates for the index, so an evenly spaced,
+// deterministic sample of the keys serves); block = 64 sampled rows,
+// thread = column
+constexpr uint32_t kNnzSampleRows = 65536;
+__global__ void k_col_nnz(const int8_t* keys, int stride, int n, uint32_t rows, uint32_t step, uint32_t* cnt) {
+  const uint32_t i0 = blockIdx.x * 64u;
+  const uint32_t i1 = min(rows, i0 + 64u);
   for (int c = threadIdx.x; c < n; c += blockDim.x) {
     uint32_t local = 0;
-    for (uint32_t r = r0; r < r1; ++r) local += keys[(size_t)r * stride + c] != 0;
+    for (uint32_t i = i0; i < i1; ++i) local += keys[(size_t)i * step * stride + c] != 0;
     if (local) atomicAdd(&cnt[c], local);
   }
 }
 
-__global__ void k_codes(const int8_t* keys, int stride, uint32_t count, Coords C, uint32_t* code,
-                        uint32_t* hist) {
-  uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= count) return;
-  const int8_t* g = keys + (size_t)p * stride;
+// base-3 sign code of every key on the index coordinates (row tiles in LDS)
+__global__ __launch_bounds__(kTileRows) void k_codes(const int8_t* keys, int stride, uint32_t count, Coords C,
+                                                     int tile_rows, uint32_t* code, uint32_t* hist) {
+  extern __shared__ __align__(16) int8_t dtile[];  // tile_rows x stride
+  const uint32_t r0 = blockIdx.x * (uint32_t)tile_rows;
+  const int rows = (int)min((uint32_t)tile_rows, count - r0);
+  const uint64_t* s64 = reinterpret_cast<const uint64_t*>(keys + (size_t)r0 * stride);
+  for (int w = threadIdx.x; w < rows * stride / 8; w += blockDim.x) reinterpret_cast<uint64_t*>(dtile)[w] = s64[w];
+  __syncthreads();
+  if ((int)threadIdx.x >= rows) return;
+  const uint32_t p = r0 + threadIdx.x;
+  const int8_t* g = dtile + threadIdx.x * stride;
   uint32_t cd = 0;
   for (int i = 0; i < C.k; ++i) {
     int v = g[C.c[i]];
@@ -631,7 +642,9 @@ hipError_t launch_filter(hipStream_t s, graver_ctx* ctx, int n, const int8_t* in
       uint32_t* cnt = (uint32_t*)ws_get(ctx, WS_F_CODE, ((size_t)U + n + 64) * 4, st);
       if (!cnt) return hipSuccess;
       hipLaunchKernelGGL(k_zero32, dim3((n + 255) / 256), dim3(256), 0, s, cnt, (uint32_t)n);
-      hipLaunchKernelGGL(k_col_nnz, dim3((U + 1023) / 1024), dim3(256), 0, s, canon, stride, n, U, cnt);
+      const uint32_t step = (U + kNnzSampleRows - 1) / kNnzSampleRows;
+      const uint32_t rows = (U + step - 1) / step;
+      hipLaunchKernelGGL(k_col_nnz, dim3((rows + 63) / 64), dim3(128), 0, s, canon, stride, n, rows, step, cnt);
       hipMemcpyAsync(hc.data(), cnt, (size_t)n * 4, hipMemcpyDeviceToHost, s);
       e = hipStreamSynchronize(s);
       if (e != hipSuccess) return e;
@@ -659,7 +672,8 @@ hipError_t launch_filter(hipStream_t s, graver_ctx* ctx, int n, const int8_t* in
   const unsigned c256 = (ncode + 1 + 255) / 256;
   hipLaunchKernelGGL(k_zero32, dim3(c256), dim3(256), 0, s, hist, ncode + 1);
   hipLaunchKernelGGL(k_zero32, dim3(c256), dim3(256), 0, s, cur, ncode + 1);
-  hipLaunchKernelGGL(k_codes, dim3(u256), dim3(256), 0, s, canon, stride, U, C, code, hist);
+  hipLaunchKernelGGL(k_codes, dim3((U + trows - 1) / trows), dim3(kTileRows), (size_t)trows * stride, s, canon, stride,
+                     U, C, trows, code, hist);
   scan_exclusive(s, hist, boff, ncode + 1, scr2);
   hipLaunchKernelGGL(k_bucket_scatter, dim3(u256), dim3(256), 0, s, code, U, boff, cur, bl);
   // the masks in bucket order go to the first half of the mask buffer (its

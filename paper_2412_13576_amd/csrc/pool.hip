@@ -88,7 +88,7 @@ __global__ void k_log_probe(LogDev log, PoolDev pool) {
   }
 }
 
-// A wave owns kCommitIters * 64 consecutive slots: it counts the claimed
+// A wave owns kCommitIters * 64 consecutive slots (4096): it counts the claimed
 // entries with ballots, takes that many pool indices with one atomic, then
 // assigns them in slot order.
 constexpr int kCommitIters = 64;
