@@ -231,7 +231,8 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 1) void k_descent_f32(DescentA
                                                                          float* __restrict__ state, PoolDev pool,
                                                                          unsigned long long* counters,
                                                                          float zrange, int64_t per,
-                                                                         int lim_uniform, LogDev log) {
+                                                                         int lim_uniform, LogDev log,
+                                                                         const float2* __restrict__ stepf) {
   extern __shared__ __align__(16) unsigned char smem[];
   floatx4* sFA = reinterpret_cast<floatx4*>(smem);
   shortx4* sFB = reinterpret_cast<shortx4*>(sFA + NB * DB * 64);
@@ -281,6 +282,10 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 1) void k_descent_f32(DescentA
   const float b1 = (float)a.beta1, b2 = (float)a.beta2, omb1 = (float)a.one_minus_b1, omb2 = (float)a.one_minus_b2;
   const float eps = (float)a.eps;
 
+  // Every load of the state is complete before the loop, whose only vector
+  // memory operations are the log stores; a wait inside the loop would also
+  // wait for those stores to reach memory.
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
   for (int k = 0; k < a.T; ++k) {
     // ---- forward Y^T = B Z^T, then signs (kept in the accumulators) ----
     floatx4 acc[NB];
@@ -349,8 +354,11 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 1) void k_descent_f32(DescentA
     cnt = xsum4(cnt);
     const bool bar = mu > 0.f && mu < 1.f;
     const float wbar = bar ? lam2 / ((mu * mu) * cnt) : 0.f;
-    const double bc1 = a.bc[2 * k], bc2 = a.bc[2 * k + 1];
-    const float step = (float)(a.lr / bc1), ib2 = (float)(1.0 / bc2);
+    // per-iteration Adam factors: a uniform read of data no launch writes,
+    // which the compiler keeps off the vector memory counter (so the wait
+    // for it does not also wait for this wave's log stores)
+    const float2 sf = stepf[k];
+    const float step = sf.x, ib2 = sf.y;
     // ---- gradient, Adam, rounding ----
     int changed = 0, inrange = 1;
     floatx4 dr[DB];
@@ -523,7 +531,7 @@ static hipError_t launch_nd(hipStream_t s, const DescentArgs& a, const float* FA
   hipLaunchKernelGGL(kern, dim3((unsigned)(nw / kWavesPerBlock)), dim3(64 * kWavesPerBlock), shmem, s, a,
                      reinterpret_cast<const floatx4*>(FA), reinterpret_cast<const shortx4*>(FA + nblk64 * 4),
                      reinterpret_cast<const shortx4*>(BA), state, pool, counters, zrange, per, lim_uniform,
-                     a.log);
+                     a.log, reinterpret_cast<const float2*>(a.stepf));
   return hipGetLastError();
 }
 

@@ -47,6 +47,7 @@ struct Job {
   graver_extract_stats stt{};
   // device buffers
   double* dbc = nullptr;
+  float* dstepf = nullptr;
   double *z = nullptr, *mm = nullptr, *vv = nullptr;
   size_t nd = 0;
   PoolDev pool{};
@@ -151,7 +152,18 @@ graver_status job_setup(graver_ctx* ctx, Job& j, bool force_big, bool autotune) 
   if (!j.dbc) return st;
   HIP_TRY(hipMemcpyAsync(j.dbc, hbc.data(), hbc.size() * sizeof(double), hipMemcpyHostToDevice, s),
           "copy bias corrections");
-  HIP_TRY(hipStreamSynchronize(s), "sync");  // hbc is a local
+  // the binary32 kernels' per-iteration factors, from the same divisions
+  // they would otherwise do in binary64 every iteration
+  std::vector<float> hsf(hbc.size());
+  for (size_t k = 0; k + 1 < hbc.size(); k += 2) {
+    hsf[k] = (float)(prm->lr / hbc[k]);
+    hsf[k + 1] = (float)(1.0 / hbc[k + 1]);
+  }
+  j.dstepf = (float*)W(ctx, j, WS_STEPF, hsf.size() * sizeof(float), &st);
+  if (!j.dstepf) return st;
+  HIP_TRY(hipMemcpyAsync(j.dstepf, hsf.data(), hsf.size() * sizeof(float), hipMemcpyHostToDevice, s),
+          "copy step factors");
+  HIP_TRY(hipStreamSynchronize(s), "sync");  // hbc and hsf are locals
 
   j.nd = (size_t)N * d;
   j.z = (double*)W(ctx, j, WS_Z, j.nd * sizeof(double), &st);
@@ -222,6 +234,7 @@ graver_status job_setup(graver_ctx* ctx, Job& j, bool force_big, bool autotune) 
   da.one_minus_b1 = 1.0 - prm->beta1;
   da.one_minus_b2 = 1.0 - prm->beta2;
   da.bc = j.dbc;
+  da.stepf = j.dstepf;
   da.collect = prm->collect;
   da.bf16_iters = prm->precision == GRAVER_BF16 ? std::max(0, T - prm->polish_iters) : 0;
   da.lim_uniform = (int32_t)(j.hu[0] - j.hl[0]);
@@ -382,6 +395,7 @@ graver_status job_descend(graver_ctx* ctx, Job& j, int until) {
     DescentArgs dc = j.da;
     dc.T = c;
     dc.bc = j.dbc + 2 * (size_t)j.done;
+    dc.stepf = j.dstepf + 2 * (size_t)j.done;
     dc.bf16_iters = std::max(0, std::min(c, j.bf16_total - j.done));
     HIP_TRY(hipMemcpyAsync(j.fbak, j.fstate, j.sbytes, hipMemcpyDeviceToDevice, s), "state backup");
     HIP_TRY(hipMemcpyAsync(j.cbak, j.counters, 64, hipMemcpyDeviceToDevice, s), "counter backup");
@@ -611,6 +625,7 @@ extern "C" graver_status graver_extract_batch(graver_ctx* ctx, int32_t count, co
         DescentArgs dc = j.da;
         dc.T = pt.end - pt.begin;
         dc.bc = j.dbc + 2 * (size_t)pt.begin;
+        dc.stepf = j.dstepf + 2 * (size_t)pt.begin;
         dc.bf16_iters = pt.bf16 ? dc.T : 0;
         bjs.push_back(BigJob{dc, j.img, j.fstate, j.kscr, j.counters});
       }

@@ -87,7 +87,7 @@ enum Slot : int {
   WS_F_CODE, WS_F_HIST, WS_F_OFF, WS_F_CUR, WS_F_BL, WS_A_QFLAG, WS_LOG, WS_LOG_COUNT, WS_MF_BAK, WS_MISC2,
   WS_I_X, WS_I_M, WS_I_V, WS_I_R, WS_I_G,
   WS_S_KEYS, WS_S_F, WS_S_SOL, WS_S_FEAS, WS_S_IDX, WS_S_STARTS, WS_S_X, WS_S_FV, WS_S_STEPS, WS_S_B, WS_S_P,
-  WS_V_CSR, WS_BIG_DESC, WS_R_KEYS, WS_R_HIST,
+  WS_V_CSR, WS_BIG_DESC, WS_R_KEYS, WS_R_HIST, WS_STEPF,
   WS_END
 };
 static_assert(WS_END <= Ws::kSlots, "too many workspace slots");
@@ -129,6 +129,7 @@ struct DescentArgs {
   double lr, beta1, beta2, eps, lambda1, lambda2;
   double one_minus_b1, one_minus_b2;
   const double* bc;     // 2*T bias corrections (device): [2k] = 1-b1^t, [2k+1] = 1-b2^t
+  const float* stepf;   // 2*T (device): [2k] = (float)(lr / bc[2k]), [2k+1] = (float)(1 / bc[2k+1])
   int32_t collect;
   int32_t bf16_iters;   // MFMA path: iterations k < bf16_iters use the bf16 hi/lo forward
   int32_t lim_uniform;  // u_i - l_i when equal for every i, else -1
