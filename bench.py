@@ -91,6 +91,18 @@ def _bases(insts, lll):
         return list(ex.map(lambda it: G.kernel_basis(it[0].A, lll=it[1]), [(i, l) for i, l in zip(insts, lll)]))
 
 
+def _copy_calibration():
+    """One device-to-device copy of 1 GiB: a dispatch whose HBM bytes are
+    known, run in the profiled process to scale the FETCH_SIZE / WRITE_SIZE
+    counters of the other dispatches."""
+    import torch
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def _line(metric, value, unit, steps, warmup, ms, dtype, config, **extra):
     out = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": steps, "warmup": warmup,
            "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
@@ -347,6 +359,8 @@ def main():
               "(multi-GPU sharding is described in DESIGN.md, not run)", file=sys.stderr)
         sys.exit(2)
 
+    if args.copy_calibration:
+        _copy_calibration()
     if args.config != "qp":
         {"precision": bench_precision, "batch": bench_batch, "serve": bench_serve,
          "augment": bench_augment}[args.config](args)
@@ -379,12 +393,6 @@ def main():
         x, f, steps, best = G.augment(ctx, prob, obj, F, starts)
         return keys.shape[0], F.shape[0], st, f, steps, best
 
-    if args.copy_calibration:
-        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
     for w in range(args.warmup):
         step(1000 + w)
     torch.cuda.synchronize()
