@@ -101,7 +101,11 @@ constexpr int kEvalThreads = 256;
 constexpr int kStartGroup = 16;  // 2 bits per start in a 32-bit feasibility mask
 
 // q_g of one direction (ascending sums over its support), computed the
-// first time some start can move along g and cached for the call.
+// first time some start can move along g and cached for the call.  The
+// cache holds kQgUnset until then; a cached value is one 64-bit word read
+// and written with relaxed atomics (q_g is a function of g and Q alone, so
+// a thread that misses the cache computes the same bits).
+constexpr uint64_t kQgUnset = 0x7FF4A3C5E1F00D01ull;  // a NaN payload no binary64 arithmetic produces
 __device__ double qg_of(const int8_t* g, int n, const double* Q) {
   double q = 0.0;
   for (int i = 0; i < n; ++i) {
@@ -132,16 +136,18 @@ __device__ __forceinline__ void wave_best(Move& b) {
 // +g or -g exists only if lambda = 1 is feasible (the box is convex and x
 // is inside it), which is tested first with an early exit; lambda_max,
 // a_g and q_g are computed only for feasible directions.
-__global__ void k_eval(AugArgs a, const int64_t* X, const uint32_t* done, const double* R, double* qg,
-                       uint32_t* qflag, const double* tab, int w, Move* partial) {
+__global__ void k_eval(AugArgs a, const int64_t* X, const uint32_t* done, const double* R, uint64_t* qg,
+                       const double* tab, int w, int lds_r, Move* partial) {
   const int n = a.n;
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   const int s0 = blockIdx.y * kStartGroup;
   const int8_t* g = a.dirs + (size_t)(k < a.K ? k : 0) * n;
   __shared__ Move sh[kStartGroup][kEvalThreads / 64];
-  // slacks of the group's starts, clamped to 127: x_i + g_i stays in
-  // [l_i, u_i] iff -dn_i <= g_i <= up_i, and |g_i| <= 127 keeps the test exact
-  extern __shared__ int8_t slack[];  // [kStartGroup][2][n]: up, then dn
+  // slacks of the group's starts as int8 (exact: every width u_i - l_i is
+  // at most 127); x_i + g_i stays in [l_i, u_i] iff -dn_i <= g_i <= up_i.
+  // With lds_r the group's r rows follow them.
+  extern __shared__ __align__(16) int8_t slack[];  // [kStartGroup][2][n]: up, then dn
+  double* sR = reinterpret_cast<double*>(slack + ((size_t)kStartGroup * 2 * n + 15) / 16 * 16);
   for (int t = threadIdx.x; t < kStartGroup * n; t += blockDim.x) {
     const int si = t / n, i = t % n, s = s0 + si;
     int64_t up = 0, dn = 0;
@@ -149,9 +155,10 @@ __global__ void k_eval(AugArgs a, const int64_t* X, const uint32_t* done, const 
       const int64_t xi = X[(size_t)s * n + i];
       up = a.u[i] - xi;
       dn = xi - a.l[i];
+      if (lds_r) sR[t] = R[(size_t)s * n + i];
     }
-    slack[(size_t)si * 2 * n + i] = (int8_t)(up < 127 ? up : 127);
-    slack[(size_t)si * 2 * n + n + i] = (int8_t)(dn < 127 ? dn : 127);
+    slack[(size_t)si * 2 * n + i] = (int8_t)up;
+    slack[(size_t)si * 2 * n + n + i] = (int8_t)dn;
   }
   __syncthreads();
   // lambda = 1 feasibility of +g and -g for every start of the group in one
@@ -195,34 +202,37 @@ __global__ void k_eval(AugArgs a, const int64_t* X, const uint32_t* done, const 
     if (s < a.S && !done[s] && k < a.K) {
       const int64_t* x = X + (size_t)s * n;
       if (any && (fp || fn)) {
-        int64_t lp = INT64_MAX, ln = INT64_MAX;
+        // lambda_max of +g and -g and, for a quadratic, a_g = sum g_i r_i in
+        // one pass over the support of g (ascending i)
+        const double* r = lds_r ? sR + (size_t)si * n : R + (size_t)s * n;
+        const bool quad = a.kind == GRAVER_F_QUADRATIC;
+        // the slacks are exact: every width u_i - l_i is at most 127 (int8
+        // keys; the entry points reject wider boxes)
+        const int8_t* su = slack + (size_t)si * 2 * n;
+        const int8_t* sd = su + n;
+        int lpi = INT_MAX, lni = INT_MAX;
+        double ag = 0.0;
         for (int i = 0; i < n; ++i) {
           const int gi = g[i];
           if (gi == 0) continue;
-          const int64_t up = a.u[i] - x[i], dn = x[i] - a.l[i];
+          const int up = su[i], dn = sd[i];
           if (gi > 0) {
-            lp = min(lp, up / gi);
-            ln = min(ln, dn / gi);
+            lpi = min(lpi, up / gi);
+            lni = min(lni, dn / gi);
           } else {
-            lp = min(lp, dn / (-gi));
-            ln = min(ln, up / (-gi));
+            lpi = min(lpi, dn / (-gi));
+            lni = min(lni, up / (-gi));
           }
+          if (quad) ag = ag + (double)gi * r[i];
         }
-        const double* r = R + (size_t)s * n;
-        if (a.kind == GRAVER_F_QUADRATIC) {
-          double ag = 0.0;
-          for (int i = 0; i < n; ++i) {
-            const int gi = g[i];
-            if (gi != 0) ag = ag + (double)gi * r[i];
+        const int64_t lp = lpi, ln = lni;
+        if (quad) {
+          uint64_t qbits = __hip_atomic_load(&qg[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (qbits == kQgUnset) {
+            qbits = __double_as_longlong(qg_of(g, n, a.Q));
+            __hip_atomic_store(&qg[k], qbits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           }
-          double q;
-          if (__hip_atomic_load(&qflag[k], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) {
-            q = __hip_atomic_load(&qg[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          } else {
-            q = qg_of(g, n, a.Q);
-            __hip_atomic_store(&qg[k], q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&qflag[k], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-          }
+          const double q = __longlong_as_double(qbits);
           for (int sg = 0; sg < 2; ++sg) {
             const int64_t lm = sg ? ln : lp;
             const double av = sg ? -ag : ag;
@@ -399,9 +409,10 @@ graver_status run_augment(graver_ctx* ctx, const AugArgs& a, const int64_t* x_st
   hipLaunchKernelGGL(k_copy_i64, dim3((unsigned)((sn + 255) / 256)), dim3(256), 0, s, x_starts, x_out, sn);
   hipLaunchKernelGGL(k_zero_u32, dim3((S + 255) / 256), dim3(256), 0, s, done, (size_t)S);
   hipLaunchKernelGGL(k_zero_i64, dim3((S + 255) / 256), dim3(256), 0, s, steps_out, (size_t)S);
-  uint32_t* qflag = (uint32_t*)ws_get(ctx, WS_A_QFLAG, (size_t)(K > 0 ? K : 1) * 4 + 64, &st);
-  if (!qflag) return st;
-  if (K > 0) hipLaunchKernelGGL(k_zero_u32, dim3((K + 255) / 256), dim3(256), 0, s, qflag, (size_t)K);
+  if (K > 0) launch_fill_u64(s, reinterpret_cast<uint64_t*>(qg), (uint64_t)K, kQgUnset);
+  // the group's r rows go to LDS next to the slacks while they fit
+  const int lds_r = a.kind == GRAVER_F_QUADRATIC && n <= 256 ? 1 : 0;
+  const size_t eval_shm = ((size_t)kStartGroup * 2 * n + 15) / 16 * 16 + (lds_r ? (size_t)kStartGroup * n * 8 : 0);
 
   uint32_t* active = bad + 4;
   if (K > 0) {
@@ -409,8 +420,8 @@ graver_status run_augment(graver_ctx* ctx, const AugArgs& a, const int64_t* x_st
       hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, active, (size_t)1);
       hipLaunchKernelGGL(k_prepare, dim3((n + 127) / 128, S), dim3(128), 0, s, a, x_out, done, tab, w, R);
       hipLaunchKernelGGL(k_eval, dim3(nblk, (S + kStartGroup - 1) / kStartGroup), dim3(kEvalThreads),
-                         (size_t)kStartGroup * 2 * n, s, a,
-                         x_out, done, R, qg, qflag, tab, w, partial);
+                         eval_shm, s, a, x_out, done, R, reinterpret_cast<uint64_t*>(qg), tab, w, lds_r,
+                         partial);
       hipLaunchKernelGGL(k_pick, dim3(S), dim3(256), 0, s, a, nblk, partial, x_out, done, steps_out, active);
       uint32_t hact = 0;
       hipMemcpyAsync(&hact, active, 4, hipMemcpyDeviceToHost, s);
