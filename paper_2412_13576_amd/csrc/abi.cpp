@@ -31,8 +31,8 @@ void* ws_get(graver_ctx* ctx, Ws& w, int slot, size_t bytes, graver_status* st) 
   if (bytes == 0) bytes = 256;
   if (w.cap[slot] >= bytes) return w.buf[slot];
   if (w.buf[slot]) {
-    hipStreamSynchronize(ctx->stream);
-    hipFree(w.buf[slot]);
+    (void)hipStreamSynchronize(ctx->stream);  // errors surface on the next checked call
+    (void)hipFree(w.buf[slot]);
     w.buf[slot] = nullptr;
     w.cap[slot] = 0;
   }
@@ -56,7 +56,7 @@ void* ws_get(graver_ctx* ctx, int slot, size_t bytes, graver_status* st) {
 void ws_free(Ws& w) {
   for (int i = 0; i < Ws::kSlots; ++i)
     if (w.buf[i]) {
-      hipFree(w.buf[i]);
+      (void)hipFree(w.buf[i]);
       w.buf[i] = nullptr;
       w.cap[i] = 0;
     }
@@ -126,8 +126,8 @@ graver_status graver_ctx_create(graver_ctx** out, int32_t device) {
 
 void graver_ctx_destroy(graver_ctx* ctx) {
   if (!ctx) return;
-  hipSetDevice(ctx->device);
-  hipStreamSynchronize(ctx->stream);
+  (void)hipSetDevice(ctx->device);  // teardown: nothing to report to
+  (void)hipStreamSynchronize(ctx->stream);
   ws_free(ctx->ws);
   for (Ws* w : ctx->batch_ws) {
     ws_free(*w);
@@ -135,7 +135,7 @@ void graver_ctx_destroy(graver_ctx* ctx) {
   }
   solve_cache_free(ctx);
   tile_cache_free(ctx);
-  if (ctx->capture_stream) hipStreamDestroy(ctx->capture_stream);
+  if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
   delete ctx;
 }
 
@@ -159,7 +159,7 @@ graver_status graver_filter(graver_ctx* ctx, int32_t n, const int8_t* keys_in, i
     return set_error(GRAVER_E_INVALID, "bad n or count");
   if (count_in > 0 && !keys_in) return set_error(GRAVER_E_INVALID, "keys_in is NULL");
   if (keys_cap < 0 || (keys_cap > 0 && !keys_out)) return set_error(GRAVER_E_INVALID, "bad output buffer");
-  hipSetDevice(ctx->device);
+  HIP_TRY(hipSetDevice(ctx->device), "set device");
   graver_status st = GRAVER_OK;
   hipError_t e = launch_filter(ctx->stream, ctx, n, keys_in, count_in, keys_out, keys_cap, count_out, &st);
   if (st != GRAVER_OK) return st;
@@ -172,7 +172,7 @@ graver_status graver_augment(graver_ctx* ctx, const graver_problem* prob, const 
                              const graver_augment_params* params, int64_t* x_out, double* f_out,
                              int64_t* steps_out, int32_t* best_out) {
   if (!ctx || !f || !params) return set_error(GRAVER_E_INVALID, "NULL argument");
-  hipSetDevice(ctx->device);
+  HIP_TRY(hipSetDevice(ctx->device), "set device");
   std::vector<int64_t> hl, hu;
   graver_status st = validate_problem(ctx, prob, true, hl, hu);
   if (st != GRAVER_OK) return st;
@@ -218,7 +218,7 @@ graver_status graver_init_solutions(graver_ctx* ctx, const graver_problem* prob,
                                     double* x_out, int64_t* sol_out, int32_t* feasible_out,
                                     int64_t* n_feasible) {
   if (!ctx || !prm || !sol_out || !feasible_out) return set_error(GRAVER_E_INVALID, "NULL argument");
-  hipSetDevice(ctx->device);
+  HIP_TRY(hipSetDevice(ctx->device), "set device");
   if (!prob) return set_error(GRAVER_E_INVALID, "problem is NULL");
   if (prob->m < 1 || prob->n < 1 || prob->n > 4096)
     return set_error(GRAVER_E_INVALID, "need m >= 1 and 1 <= n <= 4096");

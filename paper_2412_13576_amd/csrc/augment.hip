@@ -386,7 +386,7 @@ graver_status run_augment(graver_ctx* ctx, const AugArgs& a, const int64_t* x_st
                      a.l, a.u,
                      x_starts, bad);
   unsigned int hbad = 0;
-  hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, s);
+  HIP_TRY(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, s), "augment start check");
   hipError_t e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_error(e, "augment start check");
   if (hbad) return set_error(GRAVER_E_INFEASIBLE_START, "a start violates A x = b or l <= x <= u");
@@ -396,9 +396,9 @@ graver_status run_augment(graver_ctx* ctx, const AugArgs& a, const int64_t* x_st
   double* tab = nullptr;
   if (a.kind == GRAVER_F_SEPARABLE_POLY) {
     std::vector<int64_t> hl(n), hu(n);
-    hipMemcpyAsync(hl.data(), a.l, n * 8, hipMemcpyDeviceToHost, s);
-    hipMemcpyAsync(hu.data(), a.u, n * 8, hipMemcpyDeviceToHost, s);
-    hipStreamSynchronize(s);
+    HIP_TRY(hipMemcpyAsync(hl.data(), a.l, n * 8, hipMemcpyDeviceToHost, s), "bounds");
+    HIP_TRY(hipMemcpyAsync(hu.data(), a.u, n * 8, hipMemcpyDeviceToHost, s), "bounds");
+    HIP_TRY(hipStreamSynchronize(s), "bounds");
     for (int i = 0; i < n; ++i) w = (int)std::max<int64_t>(w, hu[i] - hl[i] + 1);
     tab = (double*)ws_get(ctx, WS_A_TAB, (size_t)n * w * 8, &st);
     if (!tab) return st;
@@ -409,14 +409,14 @@ graver_status run_augment(graver_ctx* ctx, const AugArgs& a, const int64_t* x_st
   hipLaunchKernelGGL(k_copy_i64, dim3((unsigned)((sn + 255) / 256)), dim3(256), 0, s, x_starts, x_out, sn);
   hipLaunchKernelGGL(k_zero_u32, dim3((S + 255) / 256), dim3(256), 0, s, done, (size_t)S);
   hipLaunchKernelGGL(k_zero_i64, dim3((S + 255) / 256), dim3(256), 0, s, steps_out, (size_t)S);
-  if (K > 0) launch_fill_u64(s, reinterpret_cast<uint64_t*>(qg), (uint64_t)K, kQgUnset);
+  if (K > 0) HIP_TRY(launch_fill_u64(s, reinterpret_cast<uint64_t*>(qg), (uint64_t)K, kQgUnset), "q_g cache");
   // the group's r rows go to LDS next to the slacks while they fit
   const int lds_r = a.kind == GRAVER_F_QUADRATIC && n <= 256 ? 1 : 0;
   const size_t eval_shm = ((size_t)kStartGroup * 2 * n + 15) / 16 * 16 + (lds_r ? (size_t)kStartGroup * n * 8 : 0);
 
   uint32_t* active = bad + 4;
   if (K > 0) {
-    for (int64_t step = 0;; ++step) {
+    for (;;) {
       hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, active, (size_t)1);
       hipLaunchKernelGGL(k_prepare, dim3((n + 127) / 128, S), dim3(128), 0, s, a, x_out, done, tab, w, R);
       hipLaunchKernelGGL(k_eval, dim3(nblk, (S + kStartGroup - 1) / kStartGroup), dim3(kEvalThreads),
@@ -424,7 +424,7 @@ graver_status run_augment(graver_ctx* ctx, const AugArgs& a, const int64_t* x_st
                          partial);
       hipLaunchKernelGGL(k_pick, dim3(S), dim3(256), 0, s, a, nblk, partial, x_out, done, steps_out, active);
       uint32_t hact = 0;
-      hipMemcpyAsync(&hact, active, 4, hipMemcpyDeviceToHost, s);
+      HIP_TRY(hipMemcpyAsync(&hact, active, 4, hipMemcpyDeviceToHost, s), "augment step");
       e = hipStreamSynchronize(s);
       if (e != hipSuccess) return hip_error(e, "augment step");
       if (!hact) break;
@@ -433,7 +433,7 @@ graver_status run_augment(graver_ctx* ctx, const AugArgs& a, const int64_t* x_st
   hipLaunchKernelGGL(k_fval, dim3(S), dim3(256), 0, s, a, x_out, R, f_out);
   hipLaunchKernelGGL(k_best, dim3(1), dim3(64), 0, s, S, f_out, dbest);
   int32_t hb = 0;
-  hipMemcpyAsync(&hb, dbest, 4, hipMemcpyDeviceToHost, s);
+  HIP_TRY(hipMemcpyAsync(&hb, dbest, 4, hipMemcpyDeviceToHost, s), "augment objective");
   e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_error(e, "augment objective");
   if (best_out) *best_out = hb;

@@ -288,7 +288,7 @@ hipError_t launch_init_sol(hipStream_t s, const InitArgs& a, const double* x0, u
                            int32_t* feas, unsigned int* nfeas) {
   (void)R;
   if (x0) {
-    hipMemcpyAsync(X, x0, (size_t)a.S * a.n * sizeof(double), hipMemcpyDeviceToDevice, s);
+    HIP_RET(hipMemcpyAsync(X, x0, (size_t)a.S * a.n * sizeof(double), hipMemcpyDeviceToDevice, s));
   } else {
     hipLaunchKernelGGL(k_box_points, dim3((unsigned)((a.S + 255) / 256)), dim3(256), 0, s, a.n, a.S, a.l, a.u,
                        seed, first, gscratch, 1);

@@ -533,7 +533,7 @@ extern "C" graver_status graver_extract(graver_ctx* ctx, const graver_problem* p
                                         int8_t* keys_out, int64_t keys_cap, int64_t* count_out,
                                         graver_extract_stats* stats) {
   if (!ctx || !prm || !count_out) return set_error(GRAVER_E_INVALID, "NULL argument");
-  hipSetDevice(ctx->device);
+  HIP_TRY(hipSetDevice(ctx->device), "set device");
   Job j;
   j.prob = prob;
   j.prm = prm;
@@ -558,7 +558,7 @@ extern "C" graver_status graver_extract_batch(graver_ctx* ctx, int32_t count, co
   if (count < 1 || count > 4096) return set_error(GRAVER_E_INVALID, "need 1 <= count <= 4096");
   for (int i = 0; i < count; ++i)
     if (params[i].collect && (!keys_out || !keys_cap)) return set_error(GRAVER_E_INVALID, "keys_out / keys_cap");
-  hipSetDevice(ctx->device);
+  HIP_TRY(hipSetDevice(ctx->device), "set device");
   hipStream_t s = ctx->stream;
   while ((int)ctx->batch_ws.size() < count) ctx->batch_ws.push_back(new Ws());
   std::vector<Job> jobs(count);
@@ -613,7 +613,6 @@ extern "C" graver_status graver_extract_batch(graver_ctx* ctx, int32_t count, co
     };
     std::vector<Launch> launches;
     launches.reserve(groups.size());
-    int gi = 0;
     for (auto& kv : groups) {
       Launch L;
       L.sh = jobs[parts[kv.second[0]].job].sh;
@@ -637,7 +636,6 @@ extern "C" graver_status graver_extract_batch(graver_ctx* ctx, int32_t count, co
       if (!L.dev) return st;
       L.count = (int)bjs.size();
       launches.push_back(std::move(L));
-      ++gi;
     }
     // Descriptor tables first (host memory; not part of a graph).
     for (Launch& L : launches)
@@ -674,19 +672,19 @@ extern "C" graver_status graver_extract_batch(graver_ctx* ctx, int32_t count, co
       graver_status est = enqueue(cs);
       hipError_t ce = hipStreamEndCapture(cs, &graph);
       if (est != GRAVER_OK) {
-        if (graph) hipGraphDestroy(graph);
+        if (graph) (void)hipGraphDestroy(graph);
         return est;
       }
       if (ce != hipSuccess) return hip_error(ce, "end capture");
       hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
       if (ie != hipSuccess) {
-        hipGraphDestroy(graph);
+        (void)hipGraphDestroy(graph);
         return hip_error(ie, "graph instantiate");
       }
       hipError_t le = hipGraphLaunch(exec, s);
       hipError_t se = hipStreamSynchronize(s);
-      hipGraphExecDestroy(exec);
-      hipGraphDestroy(graph);
+      (void)hipGraphExecDestroy(exec);
+      (void)hipGraphDestroy(graph);
       if (le != hipSuccess) return hip_error(le, "graph launch");
       if (se != hipSuccess) return hip_error(se, "graph sync");
       ++bs.graphs;

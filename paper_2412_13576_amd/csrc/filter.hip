@@ -589,12 +589,12 @@ hipError_t launch_filter(hipStream_t s, graver_ctx* ctx, int n, const int8_t* in
                      (int64_t)cnt, n, stride, trows, canon);
   uint64_t* spk = (uint64_t*)ws_get(ctx, WS_SORT_TMP, (size_t)p2 * 8, st);
   if (!spk) return hipSuccess;
-  launch_sort_keys(s, canon, stride, cnt, idx, spk);
+  HIP_RET(launch_sort_keys(s, canon, stride, cnt, idx, spk));
   hipLaunchKernelGGL(k_mark_unique, dim3(b256), dim3(256), 0, s, canon, stride, idx, spk, cnt, flag);
   scan_exclusive(s, flag, pos, cnt, scr);
   uint32_t hlast[2] = {0, 0};
-  hipMemcpyAsync(&hlast[0], pos + cnt - 1, 4, hipMemcpyDeviceToHost, s);
-  hipMemcpyAsync(&hlast[1], flag + cnt - 1, 4, hipMemcpyDeviceToHost, s);
+  HIP_RET(hipMemcpyAsync(&hlast[0], pos + cnt - 1, 4, hipMemcpyDeviceToHost, s));
+  HIP_RET(hipMemcpyAsync(&hlast[1], flag + cnt - 1, 4, hipMemcpyDeviceToHost, s));
   hipError_t e = hipStreamSynchronize(s);
   if (e != hipSuccess) return e;
   const uint32_t U = hlast[0] + hlast[1];
@@ -645,7 +645,7 @@ hipError_t launch_filter(hipStream_t s, graver_ctx* ctx, int n, const int8_t* in
       const uint32_t step = (U + kNnzSampleRows - 1) / kNnzSampleRows;
       const uint32_t rows = (U + step - 1) / step;
       hipLaunchKernelGGL(k_col_nnz, dim3((rows + 63) / 64), dim3(128), 0, s, canon, stride, n, rows, step, cnt);
-      hipMemcpyAsync(hc.data(), cnt, (size_t)n * 4, hipMemcpyDeviceToHost, s);
+      HIP_RET(hipMemcpyAsync(hc.data(), cnt, (size_t)n * 4, hipMemcpyDeviceToHost, s));
       e = hipStreamSynchronize(s);
       if (e != hipSuccess) return e;
     }
@@ -699,8 +699,8 @@ hipError_t launch_filter(hipStream_t s, graver_ctx* ctx, int n, const int8_t* in
   // survivors back in lexicographic order: flags to lex positions, then compact uniq
   hipLaunchKernelGGL(k_scatter_flags, dim3(u256), dim3(256), 0, s, idx, alive, U, flag);
   scan_exclusive(s, flag, pos, U, scr);
-  hipMemcpyAsync(&hlast[0], pos + U - 1, 4, hipMemcpyDeviceToHost, s);
-  hipMemcpyAsync(&hlast[1], flag + U - 1, 4, hipMemcpyDeviceToHost, s);
+  HIP_RET(hipMemcpyAsync(&hlast[0], pos + U - 1, 4, hipMemcpyDeviceToHost, s));
+  HIP_RET(hipMemcpyAsync(&hlast[1], flag + U - 1, 4, hipMemcpyDeviceToHost, s));
   e = hipStreamSynchronize(s);
   if (e != hipSuccess) return e;
   const uint32_t R = hlast[0] + hlast[1];

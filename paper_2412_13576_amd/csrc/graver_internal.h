@@ -39,6 +39,12 @@ graver_status hip_error(hipError_t e, const char* what);
     hipError_t e_ = (expr);                               \
     if (e_ != hipSuccess) return hip_error(e_, what);     \
   } while (0)
+// the same inside functions that return a hipError_t
+#define HIP_RET(expr)                                     \
+  do {                                                    \
+    hipError_t e_ = (expr);                               \
+    if (e_ != hipSuccess) return e_;                      \
+  } while (0)
 
 template <class T>
 graver_status copy_to_host(graver_ctx* ctx, std::vector<T>& dst, const T* src, size_t count) {
@@ -54,21 +60,22 @@ graver_status copy_to_host(graver_ctx* ctx, std::vector<T>& dst, const T* src, s
 struct EventTimer {
   hipEvent_t a = nullptr, b = nullptr;
   hipStream_t s;
+  // timing only: a failed event call leaves the time at 0 and is not an error
   explicit EventTimer(hipStream_t st) : s(st) {
-    hipEventCreate(&a);
-    hipEventCreate(&b);
-    hipEventRecord(a, s);
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&b);
+    (void)hipEventRecord(a, s);
   }
   double stop_ms() {
     float ms = 0.f;
-    hipEventRecord(b, s);
-    hipEventSynchronize(b);
-    hipEventElapsedTime(&ms, a, b);
+    (void)hipEventRecord(b, s);
+    (void)hipEventSynchronize(b);
+    (void)hipEventElapsedTime(&ms, a, b);
     return ms;
   }
   ~EventTimer() {
-    hipEventDestroy(a);
-    hipEventDestroy(b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
   }
 };
 

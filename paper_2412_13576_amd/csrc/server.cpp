@@ -170,7 +170,7 @@ struct DevBuf {
     return static_cast<T*>(p);
   }
   ~DevBuf() {
-    for (void* p : ptrs) hipFree(p);
+    for (void* p : ptrs) (void)hipFree(p);
   }
 };
 
@@ -186,7 +186,9 @@ struct Live {
 template <class T>
 T* upload(DevBuf& db, hipStream_t s, const std::vector<T>& v) {
   T* p = db.alloc<T>(v.size());
-  if (p && !v.empty()) hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
+  // a failed copy is reported like a failed allocation (nullptr)
+  if (p && !v.empty() && hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s) != hipSuccess)
+    return nullptr;
   return p;
 }
 
@@ -212,14 +214,15 @@ graver_status finish_request(graver_ctx* ctx, Live& L, DevBuf& db) {
   r.res.feasible_starts = nfeas;
   std::vector<int32_t> hf((size_t)std::max<int64_t>(S, 0));
   if (S > 0) {
-    hipMemcpyAsync(hf.data(), feas, S * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    HIP_TRY(hipMemcpyAsync(hf.data(), feas, S * sizeof(int32_t), hipMemcpyDeviceToHost, s), "feasibility flags");
     hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_error(e, "feasibility flags");
   }
   std::vector<int64_t> hsol;
   if (nfeas > 0) {
     hsol.resize((size_t)S * n);
-    hipMemcpyAsync(hsol.data(), sol, hsol.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s);
+    HIP_TRY(hipMemcpyAsync(hsol.data(), sol, hsol.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s),
+            "initial solutions");
     hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_error(e, "initial solutions");
   }
@@ -241,9 +244,10 @@ graver_status finish_request(graver_ctx* ctx, Live& L, DevBuf& db) {
   std::vector<int64_t> hs(S2);
   r.x_best.assign(n, 0);
   double fb = 0.0;
-  hipMemcpyAsync(hs.data(), so, S2 * sizeof(int64_t), hipMemcpyDeviceToHost, s);
-  hipMemcpyAsync(&fb, fo + best, sizeof(double), hipMemcpyDeviceToHost, s);
-  hipMemcpyAsync(r.x_best.data(), xo + (size_t)best * n, n * sizeof(int64_t), hipMemcpyDeviceToHost, s);
+  HIP_TRY(hipMemcpyAsync(hs.data(), so, S2 * sizeof(int64_t), hipMemcpyDeviceToHost, s), "best-of");
+  HIP_TRY(hipMemcpyAsync(&fb, fo + best, sizeof(double), hipMemcpyDeviceToHost, s), "best-of");
+  HIP_TRY(hipMemcpyAsync(r.x_best.data(), xo + (size_t)best * n, n * sizeof(int64_t), hipMemcpyDeviceToHost, s),
+          "best-of");
   hipError_t e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_error(e, "best-of");
   r.res.f_best = fb;
@@ -252,7 +256,7 @@ graver_status finish_request(graver_ctx* ctx, Live& L, DevBuf& db) {
 }
 
 void gpu_worker(graver_server* s) {
-  hipSetDevice(s->prm.device);
+  (void)hipSetDevice(s->prm.device);  // graver_ctx_create below checks the device
   graver_ctx* ctx = nullptr;
   hipStream_t stream = nullptr;
   const bool ok = graver_ctx_create(&ctx, s->prm.device) == GRAVER_OK &&
@@ -327,7 +331,8 @@ void gpu_worker(graver_server* s) {
         L.keys = db.alloc<int8_t>((size_t)r.ex.pool_capacity * r.n);
         if (!L.prob.A || !L.prob.B || !L.keys) bst = set_error(GRAVER_E_NOMEM, "device allocation failed");
       }
-      if (bst == GRAVER_OK) hipStreamSynchronize(stream);  // host vectors of the uploads stay alive anyway
+      if (bst == GRAVER_OK && hipStreamSynchronize(stream) != hipSuccess)
+        bst = set_error(GRAVER_E_DEVICE, "uploading the batch's instances failed");
       // one batched extraction; on failure every request is retried alone so
       // that one request's error does not fail the others
       if (bst == GRAVER_OK) {
@@ -370,7 +375,7 @@ void gpu_worker(graver_server* s) {
         for (auto& r : batch) r->res.status = bst;
       }
       // release the batch's device memory (request buffers and workspaces)
-      hipStreamSynchronize(stream);
+      (void)hipStreamSynchronize(stream);  // each request already holds its status
       ws_free(ctx->ws);
       for (Ws* w : ctx->batch_ws) ws_free(*w);
     }
@@ -386,7 +391,7 @@ void gpu_worker(graver_server* s) {
     s->cv_ready.notify_all();
   }
   if (ctx) graver_ctx_destroy(ctx);
-  if (stream) hipStreamDestroy(stream);
+  if (stream) (void)hipStreamDestroy(stream);
 }
 
 }  // namespace

@@ -64,9 +64,9 @@ void solve_cache_free(graver_ctx* ctx) {
   if (!ctx->solve_cache) return;
   auto* c = static_cast<SolveCache*>(ctx->solve_cache);
   for (auto& e : c->entries) {
-    hipFree(e.B);
-    hipFree(e.P);
-    hipFree(e.F);
+    (void)hipFree(e.B);
+    (void)hipFree(e.P);
+    (void)hipFree(e.F);
   }
   delete c;
   ctx->solve_cache = nullptr;
@@ -80,7 +80,7 @@ extern "C" graver_status graver_solve(graver_ctx* ctx, const graver_problem* pro
                                       const graver_solve_params* prm, int64_t* x_best, double* f_best,
                                       graver_solve_stats* stats) {
   if (!ctx || !prob || !f || !prm || !x_best || !f_best) return set_error(GRAVER_E_INVALID, "NULL argument");
-  hipSetDevice(ctx->device);
+  HIP_TRY(hipSetDevice(ctx->device), "set device");
   if (prob->m < 1 || prob->n < 1 || prob->n > 4096)
     return set_error(GRAVER_E_INVALID, "need m >= 1 and 1 <= n <= 4096");
   if (!prob->A || !prob->b || !prob->l || !prob->u)
@@ -125,8 +125,8 @@ extern "C" graver_status graver_solve(graver_ctx* ctx, const graver_problem* pro
       if (!dB) return rc;
       auto* dP = (double*)ws_get(ctx, WS_S_P, (size_t)dd * n * sizeof(double), &rc);
       if (!dP) return rc;
-      hipMemcpyAsync(dB, hB.data(), (size_t)n * dd * sizeof(int64_t), hipMemcpyHostToDevice, s);
-      hipMemcpyAsync(dP, hP.data(), (size_t)dd * n * sizeof(double), hipMemcpyHostToDevice, s);
+      HIP_TRY(hipMemcpyAsync(dB, hB.data(), (size_t)n * dd * sizeof(int64_t), hipMemcpyHostToDevice, s), "basis");
+      HIP_TRY(hipMemcpyAsync(dP, hP.data(), (size_t)dd * n * sizeof(double), hipMemcpyHostToDevice, s), "basis");
       hipError_t e = hipStreamSynchronize(s);
       if (e != hipSuccess) return hip_error(e, "copy basis");
       p.B = dB;
@@ -166,9 +166,9 @@ extern "C" graver_status graver_solve(graver_ctx* ctx, const graver_problem* pro
       if ((rc = dev_alloc(&e.B, (size_t)n * d)) != GRAVER_OK) return rc;
       if ((rc = dev_alloc(&e.P, p.P ? (size_t)d * n : 1)) != GRAVER_OK) return rc;
       if ((rc = dev_alloc(&e.F, (size_t)K * n)) != GRAVER_OK) return rc;
-      hipMemcpyAsync(e.B, p.B, (size_t)n * d * sizeof(int64_t), hipMemcpyDeviceToDevice, s);
-      if (p.P) hipMemcpyAsync(e.P, p.P, (size_t)d * n * sizeof(double), hipMemcpyDeviceToDevice, s);
-      if (K) hipMemcpyAsync(e.F, F, (size_t)K * n, hipMemcpyDeviceToDevice, s);
+      HIP_TRY(hipMemcpyAsync(e.B, p.B, (size_t)n * d * sizeof(int64_t), hipMemcpyDeviceToDevice, s), "cache");
+      if (p.P) HIP_TRY(hipMemcpyAsync(e.P, p.P, (size_t)d * n * sizeof(double), hipMemcpyDeviceToDevice, s), "cache");
+      if (K) HIP_TRY(hipMemcpyAsync(e.F, F, (size_t)K * n, hipMemcpyDeviceToDevice, s), "cache");
       hipError_t err = hipStreamSynchronize(s);
       if (err != hipSuccess) return hip_error(err, "cache copy");
       cache_of(ctx)->entries.push_back(std::move(e));
@@ -207,12 +207,13 @@ extern "C" graver_status graver_solve(graver_ctx* ctx, const graver_problem* pro
   const int32_t S2 = (int32_t)(idx.size() + nx);
   auto* starts = (int64_t*)ws_get(ctx, WS_S_STARTS, (size_t)S2 * n * sizeof(int64_t), &rc);
   if (!starts) return rc;
-  hipMemcpyAsync(didx, idx.data(), idx.size() * sizeof(int32_t), hipMemcpyHostToDevice, s);
+  HIP_TRY(hipMemcpyAsync(didx, idx.data(), idx.size() * sizeof(int32_t), hipMemcpyHostToDevice, s), "start indices");
   hipError_t e = launch_gather_rows_i64(s, sol, n, didx, (int64_t)idx.size(), starts);
   if (e != hipSuccess) return hip_error(e, "gather starts");
   if (nx)
-    hipMemcpyAsync(starts + idx.size() * n, prm->x_starts, (size_t)nx * n * sizeof(int64_t),
-                   hipMemcpyDeviceToDevice, s);
+    HIP_TRY(hipMemcpyAsync(starts + idx.size() * n, prm->x_starts, (size_t)nx * n * sizeof(int64_t),
+                           hipMemcpyDeviceToDevice, s),
+            "caller starts");
   st.ms_init = ms_since(t0);
 
   // ---- augmentation and best-of -------------------------------------------
@@ -231,8 +232,9 @@ extern "C" graver_status graver_solve(graver_ctx* ctx, const graver_problem* pro
   if ((rc = to_host(ctx, hs, so, (size_t)S2)) != GRAVER_OK) return rc;
   for (int64_t v : hs) st.augment_steps += v;
   double fb = 0.0;
-  hipMemcpyAsync(&fb, fo + best, sizeof(double), hipMemcpyDeviceToHost, s);
-  hipMemcpyAsync(x_best, xo + (size_t)best * n, (size_t)n * sizeof(int64_t), hipMemcpyDeviceToDevice, s);
+  HIP_TRY(hipMemcpyAsync(&fb, fo + best, sizeof(double), hipMemcpyDeviceToHost, s), "best-of");
+  HIP_TRY(hipMemcpyAsync(x_best, xo + (size_t)best * n, (size_t)n * sizeof(int64_t), hipMemcpyDeviceToDevice, s),
+          "best-of");
   e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_error(e, "best-of");
   *f_best = fb;
