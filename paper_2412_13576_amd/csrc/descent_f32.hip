@@ -434,18 +434,30 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 1) void k_descent_f32(DescentA
     if (__ballot(emit) == 0) continue;
     // ---- box test (condition C4) and nonzero test ----
     int inbox = 1, nonzero = 0;
+    if (lim_uniform >= 0) {
+      // one width for every coordinate: the largest |g_i| decides both tests
+      int amax = 0;
 #pragma unroll
-    for (int ib = 0; ib < NB; ++ib)
+      for (int ib = 0; ib < NB; ++ib)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = 16 * ib + 4 * q + r;
-        const int g = gi[ib][r];
-        const int lim = lim_uniform >= 0 ? lim_uniform : sLim[i];
-        inbox &= (g <= lim) & (g >= -lim);
-        nonzero |= g != 0;
-      }
-    inbox = xand4(inbox);
-    nonzero = xor4(nonzero);
+        for (int r = 0; r < 4; ++r) amax = max(amax, max(gi[ib][r], -gi[ib][r]));
+      amax = max(amax, __shfl_xor(amax, 16, 64));
+      amax = max(amax, __shfl_xor(amax, 32, 64));
+      inbox = amax <= lim_uniform;
+      nonzero = amax > 0;
+    } else {
+#pragma unroll
+      for (int ib = 0; ib < NB; ++ib)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int g = gi[ib][r];
+          const int lim = sLim[16 * ib + 4 * q + r];
+          inbox &= (g <= lim) & (g >= -lim);
+          nonzero |= g != 0;
+        }
+      inbox = xand4(inbox);
+      nonzero = xor4(nonzero);
+    }
     const bool put = emit && inbox && nonzero;
     n_emit += (q == 0 && emit) ? 1 : 0;
     n_inbox += (q == 0 && put) ? 1 : 0;
