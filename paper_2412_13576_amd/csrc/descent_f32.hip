@@ -346,21 +346,29 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 1) void k_descent_f32(DescentA
 #pragma unroll
       for (int r = 0; r < 4; ++r) mu = fmaxf(mu, fabsf(z[jb][r]));
     mu = xmax4(mu);
-    float cnt = 0.f;
-#pragma unroll
-    for (int jb = 0; jb < DB; ++jb)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) cnt += fabsf(z[jb][r]) == mu ? 1.f : 0.f;
-    cnt = xsum4(cnt);
     const bool bar = mu > 0.f && mu < 1.f;
-    const float wbar = bar ? lam2 / ((mu * mu) * cnt) : 0.f;
+    // the barrier term acts only while ||z||_inf < 1, which is rare: its tie
+    // count and its gradient run only in waves where some start needs them
+    const bool wave_bar = __ballot(bar) != 0;
+    float wbar = 0.f;
+    if (wave_bar) {
+      float cnt = 0.f;
+#pragma unroll
+      for (int jb = 0; jb < DB; ++jb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) cnt += fabsf(z[jb][r]) == mu ? 1.f : 0.f;
+      cnt = xsum4(cnt);
+      wbar = bar ? lam2 / ((mu * mu) * cnt) : 0.f;
+    }
     // per-iteration Adam factors: a uniform read of data no launch writes,
     // which the compiler keeps off the vector memory counter (so the wait
     // for it does not also wait for this wave's log stores)
     const float2 sf = stepf[k];
     const float step = sf.x, ib2 = sf.y;
     // ---- gradient, Adam, rounding ----
-    int changed = 0, inrange = 1;
+    // the largest |z_j| and the largest rounding change decide the range and
+    // change flags (the same tests as per coordinate, in fewer instructions)
+    float zmax = 0.f, dmax = 0.f;
     floatx4 dr[DB];
 #pragma unroll
     for (int jb = 0; jb < DB; ++jb)
@@ -376,11 +384,14 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 1) void k_descent_f32(DescentA
         const float zn = zj - (step * mj) * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(vj * ib2) + eps);
         z[jb][r] = zn;
         const float rn = rintf(zn);
-        changed |= (rn != rp[jb][r]) | (k == 0);
-        inrange &= fabsf(zn) < zrange;
-        dr[jb][r] = rn - rp[jb][r];
+        const float d = rn - rp[jb][r];
+        dmax = fmaxf(dmax, fabsf(d));
+        zmax = fmaxf(zmax, fabsf(zn));
+        dr[jb][r] = d;
         rp[jb][r] = rn;
       }
+    int changed = (dmax > 0.f) | (k == 0);
+    int inrange = zmax < zrange;
     __builtin_amdgcn_sched_barrier(0);
     if (!a.collect) continue;
     // ---- per-start flags (the 4 lanes of a start agree afterwards) ----
