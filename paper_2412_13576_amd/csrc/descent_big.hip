@@ -222,17 +222,23 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(const BigArgs* _
 #pragma unroll
       for (int r = 0; r < 4; ++r) mu = fmaxf(mu, fabsf(z[jb][r]));
     mu = xmax4(mu);
+    // the tie count matters only while the start's norm is in (0, 1); this
+    // wave's part of the norm bounds it from below, so the count is skipped
+    // in waves where no start has this part in (0, 1)
     float cnt = 0.f;
-    int inrange = 1;
+    if (__ballot(mu > 0.f && mu < 1.f) != 0) {
+#pragma unroll
+      for (int jb = 0; jb < DBPW; ++jb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) cnt += fabsf(z[jb][r]) == mu ? 1.f : 0.f;
+      cnt = xsum4(cnt);
+    }
+    float rmax = 0.f;
 #pragma unroll
     for (int jb = 0; jb < DBPW; ++jb)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        cnt += fabsf(z[jb][r]) == mu ? 1.f : 0.f;
-        inrange &= fabsf(rintf(z[jb][r])) <= 256.f;
-      }
-    cnt = xsum4(cnt);
-    inrange = xand4(inrange);
+      for (int r = 0; r < 4; ++r) rmax = fmaxf(rmax, fabsf(rintf(z[jb][r])));
+    int inrange = xmax4(rmax) <= 256.f;
     // stage row block 0 (every read of the buffers in the previous
     // iteration ended before its last barrier); the barrier below publishes it
     dma_chunk<kChunkU4>(img, buf0);
