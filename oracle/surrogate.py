@@ -36,9 +36,6 @@ from typing import Optional, Set, Tuple
 
 import numpy as np
 
-Z_RANGE = float(2 ** 30)
-
-
 @dataclass
 class AdamParams:
     lr: float = 0.003
@@ -141,13 +138,14 @@ def round_half_even(z: np.ndarray) -> np.ndarray:
 def candidate(B: np.ndarray, r: np.ndarray) -> np.ndarray:
     """g = B r in exact integers for integer coordinate rows r (N, d)."""
     Bi = np.asarray(B, dtype=np.int64)
-    ri = r.astype(np.int64)
-    bound = int(np.abs(Bi).sum(axis=1).max(initial=0)) * int(np.abs(ri).max(initial=0))
+    rmax = float(np.abs(r).max(initial=0.0))
+    bound = int(np.abs(Bi).sum(axis=1).max(initial=0)) * int(rmax)
     if bound >= 2 ** 62:
+        # exact Python integers (r holds integral binary64 values)
         rows = [[sum(int(Bi[i, j]) * int(row[j]) for j in range(Bi.shape[1]))
-                 for i in range(Bi.shape[0])] for row in ri]
+                 for i in range(Bi.shape[0])] for row in r]
         return np.array(rows, dtype=object)
-    return ri @ Bi.T
+    return r.astype(np.int64) @ Bi.T
 
 
 def in_box(g: np.ndarray, l: np.ndarray, u: np.ndarray) -> np.ndarray:
@@ -187,10 +185,9 @@ def extract(A, B, l, u, z0: np.ndarray, iters: int, p: AdamParams,
         g = grad_phi(Bf, z, p.lambda1, p.lambda2)
         z, m, v = adam_step(z, m, v, g, t, p)
         r = round_half_even(z)
-        inrange = np.all(np.abs(z) < Z_RANGE, axis=1)
         changed = np.ones(z.shape[0], bool) if r_prev is None else np.any(r != r_prev, axis=1)
         r_prev = r
-        rows = np.nonzero(changed & inrange)[0]
+        rows = np.nonzero(changed)[0]
         if rows.size == 0:
             continue
         gs = candidate(Bi, r[rows])
