@@ -205,7 +205,6 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(const BigArgs* _
   uint32_t* srow = reinterpret_cast<uint32_t*>(g.scratch + (size_t)sidx * stride);
 
   int changed = 0;       // the current iterate's rounding differs from the previous one
-  bool alive = svalid;   // start still inside the exact range
   unsigned long long n_emit = 0, n_inbox = 0, n_range = 0;
   uint32_t lbase = 0, lused = 0;
   int lleft = 0;
@@ -270,7 +269,7 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(const BigArgs* _
     // block-uniform (the row-block loop below has block barriers, and the
     // final pass exits the loop when no wave of the block needs it).  The
     // barrier is taken on every iteration: it also publishes row block 0.
-    const bool needg = __syncthreads_or((a.collect && k > 0 && changed && alive) ? 1 : 0) != 0;
+    const bool needg = __syncthreads_or((a.collect && k > 0 && changed && svalid) ? 1 : 0) != 0;
     if (!descend && !needg) break;
     // rounded coordinates of the current iterate as exact bf16 operands
     shortx4 rp[DBPW];
@@ -402,8 +401,7 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(const BigArgs* _
     if (needg) {
       inbox = xand4(inbox);
       nonzero = xor4(nonzero);
-      const bool em = changed && alive;
-      if (em && !inrange) alive = false;
+      const bool em = changed && svalid;
       const bool emit = em && inrange;
       const bool put = lead && emit && inbox && nonzero;
       n_emit += (lead && q == 0 && emit) ? 1 : 0;
@@ -440,7 +438,9 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(const BigArgs* _
         }
       }
     }
-    if (!alive && svalid && lead && q == 0 && descend && k > 0) ++n_range;
+    // an iterate beyond the exact range yields no candidate; the next one
+    // is formed from its own r again (B r is recomputed every iteration)
+    if (needg && changed && svalid && !inrange && lead && q == 0) ++n_range;
     if (!descend) break;
 
     __builtin_amdgcn_sched_barrier(0);

@@ -27,9 +27,10 @@
 // exact candidate g = B r of every start is tracked incrementally:
 // g += B (r - r_prev) runs on the same MFMA only for the 4-column groups in
 // which some start's rounded coordinate moved; every partial sum is an
-// integer below 2^24 as long as |z_j| < floor(2^24 / max_i sum_j |B_ij|),
-// so binary32 accumulation is exact.  A start whose iterate leaves that
-// range stops collecting (counted as out of range).  When a start's r
+// integer of at most 2^24 as long as |r_j| <= floor(2^24 / max_i sum_j |B_ij|),
+// so binary32 accumulation is exact.  An iterate outside that range yields
+// no candidate (counted as out of range); g is formed from zero again at
+// the first iterate back inside it.  When a start's r
 // changed and g is nonzero and inside [l - u, u - l], its int8 key is
 // assembled in LDS and appended to the candidate log (each wave reserves
 // 64-row chunks with one atomic); a separate kernel moves the log into the
@@ -273,7 +274,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 1) void k_descent_f32(DescentA
 #pragma unroll
     for (int r = 0; r < 4; ++r) gi[ib][r] = 0;
 
-  bool alive = svalid;
+  bool exact = true;  // gi = B rp holds (it is not maintained while the iterate is out of range)
   unsigned long long n_emit = 0, n_inbox = 0, n_range = 0;
   uint32_t lbase = 0, lused = 0;
   int lleft = 0;
@@ -386,24 +387,39 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 1) void k_descent_f32(DescentA
         const float rn = rintf(zn);
         const float d = rn - rp[jb][r];
         dmax = fmaxf(dmax, fabsf(d));
-        zmax = fmaxf(zmax, fabsf(zn));
+        zmax = fmaxf(zmax, fabsf(rn));
         dr[jb][r] = d;
         rp[jb][r] = rn;
       }
     int changed = (dmax > 0.f) | (k == 0);
-    int inrange = zmax < zrange;
+    int inrange = zmax <= zrange;  // zmax: largest |r_j| of the new iterate
+    int jump = dmax > zrange;      // a step too large for an exact update of g
     __builtin_amdgcn_sched_barrier(0);
     if (!a.collect) continue;
     // ---- per-start flags (the 4 lanes of a start agree afterwards) ----
     inrange = xand4(inrange);
     changed = xor4(changed);
-    if (alive && !inrange) alive = false;
-    if (!alive) {
-      n_range += (q == 0 && svalid) ? 1 : 0;
+    jump = xor4(jump);
+    // An iterate beyond the exact range yields no candidate and g is not
+    // updated; the first iterate back in range (or one that moved by more
+    // than the range in one step) forms g = B r from zero, so every partial
+    // sum stays within the range and the set does not depend on how the run
+    // is split into launches.
+    const bool fresh = inrange && (!exact || jump);
+    if (!inrange) {
+      n_range += (q == 0 && svalid && changed) ? 1 : 0;
 #pragma unroll
       for (int jb = 0; jb < DB; ++jb) dr[jb] = floatx4{0.f, 0.f, 0.f, 0.f};
+    } else if (fresh) {
+#pragma unroll
+      for (int ib = 0; ib < NB; ++ib)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) gi[ib][r] = 0;
+#pragma unroll
+      for (int jb = 0; jb < DB; ++jb) dr[jb] = floatx4{rp[jb][0], rp[jb][1], rp[jb][2], rp[jb][3]};
     }
-    const bool emit = alive && changed;
+    exact = inrange;
+    const bool emit = svalid && inrange && changed;
     // ---- exact candidate update g += B (r - r_prev) on changed blocks ----
     // After the first step |r - r_prev| is small (an Adam step moves z by
     // about lr), so the 4 differences of a block are exact bf16 operands; the
