@@ -255,6 +255,23 @@ def feasible_walk_starts(x0: np.ndarray, dirs: np.ndarray, l: np.ndarray,
     return out
 
 
+def combination_directions(B: np.ndarray, count: int, density: float, limit: int,
+                           seed: int) -> np.ndarray:
+    """A synthetic direction set of integer kernel vectors: ``count`` sparse
+    integer combinations g = B z (z_j in {-1, 0, 1}, nonzero with probability
+    ``density``), kept when 0 < |g_i| <= limit for every i, made unique, each
+    with its first nonzero entry positive, in lexicographic order.  int64,
+    shape (K, n)."""
+    rng = _rng(seed)
+    d = B.shape[1]
+    Z = rng.integers(-1, 2, size=(count, d)) * (rng.random((count, d)) < density)
+    G = Z @ np.asarray(B, dtype=np.int64).T
+    G = G[np.all(np.abs(G) <= limit, axis=1) & np.any(G != 0, axis=1)]
+    first = G[np.arange(G.shape[0]), np.argmax(G != 0, axis=1)]
+    G = G * np.where(first < 0, -1, 1)[:, None]
+    return np.unique(G, axis=0)
+
+
 def antichain_with_sums(n: int, n_atoms: int, support: int, n_sums: int, seed: int,
                         mag: int = 3, positive: bool = False) -> tuple:
     """Key set whose minimal elements are known in closed form.

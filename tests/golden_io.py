@@ -44,3 +44,17 @@ def tiny_graver_box6():
         else:
             out[cur].add(tuple(int(x) for x in line.split()))
     return out
+
+
+def augment_golden(name):
+    """(inputs_sha256, best, rows) of an augmentation fixture; rows are
+    (moves, f bits, x_end) per start."""
+    rows = []
+    head = None
+    for line in _lines(name):
+        w = line.split()
+        if w[0] == "inputs":
+            head = (w[1], int(w[9]))
+            continue
+        rows.append((int(w[1]), int(w[2], 16), np.array([int(v) for v in w[3:]], dtype=np.int64)))
+    return head[0], head[1], rows
