@@ -37,7 +37,8 @@ typedef enum {
   GRAVER_E_POOL_FULL = -5,        /* more distinct candidates than pool_capacity */
   GRAVER_E_NOMEM = -6,            /* device allocation failed               */
   GRAVER_E_DEVICE = -7,           /* HIP runtime error                      */
-  GRAVER_E_CAPACITY = -8          /* caller's output buffer is too small    */
+  GRAVER_E_CAPACITY = -8,         /* caller's output buffer is too small    */
+  GRAVER_E_CANCELLED = -9         /* a served request was cancelled         */
 } graver_status;
 
 typedef enum {
@@ -138,6 +139,13 @@ typedef struct {
  * null stream until graver_ctx_set_stream. */
 graver_status graver_ctx_create(graver_ctx** out, int32_t device);
 void graver_ctx_destroy(graver_ctx* ctx);
+/* Releases the device workspace the context grew for earlier calls (descent
+ * state, candidate pool and log, filter and augmentation buffers; the solve
+ * cache and tuned tile shapes stay).  For pipelines whose stages each need
+ * most of the device memory, e.g. an extraction of about 1e8 candidates
+ * followed by their filter: trimming between the two frees the pool before
+ * the filter allocates.  Synchronises the context's stream first. */
+graver_status graver_ctx_trim(graver_ctx* ctx);
 /* Issue all GPU work of this context on `hip_stream` (a hipStream_t, e.g.
  * torch.cuda.current_stream().cuda_stream); NULL selects the null stream. */
 graver_status graver_ctx_set_stream(graver_ctx* ctx, void* hip_stream);
@@ -224,6 +232,17 @@ graver_status graver_extract_batch(graver_ctx* ctx, int32_t count, const graver_
  * *count_out (host) receives the count. */
 graver_status graver_filter(graver_ctx* ctx, int32_t n, const int8_t* keys_in, int64_t count_in,
                             int8_t* keys_out, int64_t keys_cap, int64_t* count_out);
+
+/* Condition C1 (Section 3) on its own: A g = 0 exactly for each of the
+ * `count` int8 rows of n bytes in keys (device), with A (device, m x n,
+ * |A_ij| < 2^31) -- the check graver_extract applies to every distinct
+ * candidate, here for a direction set the caller brings (for example one
+ * read from a file before graver_augment).  *n_bad (host, may be NULL)
+ * receives the number of rows with A g != 0; the call returns
+ * GRAVER_E_NOT_KERNEL when it is nonzero, GRAVER_E_OVERFLOW when some
+ * |A_ij| >= 2^31. */
+graver_status graver_verify(graver_ctx* ctx, int32_t m, int32_t n, const int64_t* A, const int8_t* keys,
+                            int64_t count, int64_t* n_bad);
 
 /* Multi-start augmentation (Algorithm 1 from every start; MAPE, Section
  * 3.3).  Directions: the K int8 rows `dirs` (device) and their negations,
@@ -402,6 +421,21 @@ graver_status graver_server_create(graver_server** out, const graver_server_para
 graver_status graver_server_submit(graver_server* srv, const graver_request* req, int64_t* ticket);
 /* Blocks until the request is done; x_best (host, n values, may be NULL). */
 graver_status graver_server_wait(graver_server* srv, int64_t ticket, graver_result* result, int64_t* x_best);
+/* Non-blocking form of graver_server_wait: *done (host) = 1 when the
+ * request has finished, and then result and x_best are written and the
+ * ticket is released exactly as graver_server_wait does; *done = 0 leaves
+ * everything untouched.  GRAVER_E_INVALID for an unknown or released ticket. */
+graver_status graver_server_poll(graver_server* srv, int64_t ticket, int32_t* done, graver_result* result,
+                                 int64_t* x_best);
+/* Cancels a request.  One still waiting for its basis or for admission
+ * leaves its queue at once (it holds no device memory); one already on the
+ * GPU stops at its next stage boundary (after the batched extraction it
+ * shares with others) and its device memory is released with its batch.
+ * Its result then has status GRAVER_E_CANCELLED; the ticket stays valid
+ * until graver_server_wait / _poll collects it.  *cancelled (host) = 1 when
+ * the request will end cancelled, 0 when it had already finished (its result
+ * stands).  GRAVER_E_INVALID for an unknown or released ticket. */
+graver_status graver_server_cancel(graver_server* srv, int64_t ticket, int32_t* cancelled);
 /* Finishes every submitted request, then stops the threads. */
 void graver_server_destroy(graver_server* srv);
 

@@ -15,6 +15,7 @@ namespace graver {
 
 static thread_local std::string g_last_error = "no error";
 
+
 graver_status set_error(graver_status s, const std::string& msg) {
   g_last_error = msg;
   return s;
@@ -99,6 +100,7 @@ const char* graver_status_string(graver_status s) {
     case GRAVER_E_NOMEM: return "out of device memory";
     case GRAVER_E_DEVICE: return "device error";
     case GRAVER_E_CAPACITY: return "output buffer too small";
+    case GRAVER_E_CANCELLED: return "cancelled";
   }
   return "unknown status";
 }
@@ -137,6 +139,15 @@ void graver_ctx_destroy(graver_ctx* ctx) {
   tile_cache_free(ctx);
   if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
   delete ctx;
+}
+
+graver_status graver_ctx_trim(graver_ctx* ctx) {
+  if (!ctx) return set_error(GRAVER_E_INVALID, "ctx is NULL");
+  HIP_TRY(hipSetDevice(ctx->device), "set device");
+  HIP_TRY(hipStreamSynchronize(ctx->stream), "stream synchronize");
+  ws_free(ctx->ws);
+  for (Ws* w : ctx->batch_ws) ws_free(*w);
+  return GRAVER_OK;
 }
 
 graver_status graver_ctx_set_stream(graver_ctx* ctx, void* hip_stream) {

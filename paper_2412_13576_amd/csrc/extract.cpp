@@ -20,6 +20,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <string>
 #include <vector>
 
 #include "graver_internal.h"
@@ -77,6 +78,59 @@ void* W(graver_ctx* ctx, Job& j, int slot, size_t bytes, graver_status* st) {
   return ws_get(ctx, *j.ws, slot, bytes, st);
 }
 
+// A's nonzeros as CSR (host), for the exact check A g = 0 (condition C1).
+graver_status build_csr(const std::vector<int64_t>& hA, int m, int n, std::vector<int32_t>& rp,
+                        std::vector<int32_t>& col, std::vector<int64_t>& val) {
+  rp.assign((size_t)m + 1, 0);
+  col.clear();
+  val.clear();
+  for (int i = 0; i < m; ++i) {
+    for (int c = 0; c < n; ++c) {
+      const int64_t av = hA[(size_t)i * n + c];
+      if (av <= -((int64_t)1 << 31) || av >= ((int64_t)1 << 31))
+        return set_error(GRAVER_E_OVERFLOW, "|A_ij| must be below 2^31");
+      if (av != 0) {
+        col.push_back(c);
+        val.push_back(av);
+      }
+    }
+    rp[i + 1] = (int32_t)col.size();
+  }
+  return GRAVER_OK;
+}
+
+// Condition C1 on the device for `count` key rows of `stride` bytes: the
+// number of rows with A g != 0 goes to *nbad (host).
+graver_status verify_rows(graver_ctx* ctx, Ws& w, int m, const std::vector<int32_t>& rp,
+                          const std::vector<int32_t>& col, const std::vector<int64_t>& val, const int8_t* keys,
+                          int n, int stride, uint32_t count, unsigned int* nbad) {
+  hipStream_t s = ctx->stream;
+  graver_status st = GRAVER_OK;
+  unsigned int* bad = (unsigned int*)ws_get(ctx, w, WS_FLAGS, 64, &st);
+  if (!bad) return st;
+  const size_t nnz = col.size();
+  const size_t ints = ((size_t)m + 1 + nnz + 1) / 2 * 2;  // int32 part, padded to 8 bytes
+  auto* csr = (int32_t*)ws_get(ctx, w, WS_V_CSR, ints * 4 + std::max<size_t>(nnz, 1) * 8, &st);
+  if (!csr) return st;
+  HIP_TRY(hipMemcpyAsync(csr, rp.data(), rp.size() * 4, hipMemcpyHostToDevice, s), "csr");
+  if (nnz) {
+    HIP_TRY(hipMemcpyAsync(csr + m + 1, col.data(), nnz * 4, hipMemcpyHostToDevice, s), "csr");
+    HIP_TRY(hipMemcpyAsync(csr + ints, val.data(), nnz * 8, hipMemcpyHostToDevice, s), "csr");
+  }
+  PoolDev view{};
+  view.keys = const_cast<int8_t*>(keys);
+  view.n = n;
+  view.stride = stride;
+  HIP_TRY(launch_verify(s, view, count, m, (int64_t)nnz, csr, csr + m + 1, reinterpret_cast<const int64_t*>(csr + ints),
+                        bad),
+          "verify");
+  unsigned int hbad = 0;
+  HIP_TRY(hipMemcpyAsync(&hbad, bad, sizeof(hbad), hipMemcpyDeviceToHost, s), "verify flag");
+  HIP_TRY(hipStreamSynchronize(s), "verify");  // rp, col, val are the caller's host vectors
+  *nbad = hbad;
+  return GRAVER_OK;
+}
+
 // Validation, host checks and the device setup of one job (everything
 // before its first descent launch).  force_big routes an MFMA job through
 // the large-basis kernel even when the small one would fit; autotune picks
@@ -112,22 +166,10 @@ graver_status job_setup(graver_ctx* ctx, Job& j, bool force_big, bool autotune) 
 
   // B must be a kernel basis: A B = 0 exactly.  A's nonzeros (CSR) serve
   // the exact check of the collected candidates.
-  j.csr_rp.assign((size_t)m + 1, 0);
   {
     std::vector<int64_t> hA, hB;
     if ((st = copy_to_host(ctx, hA, prob->A, (size_t)m * n)) != GRAVER_OK) return st;
-    for (int i = 0; i < m; ++i) {
-      for (int c = 0; c < n; ++c) {
-        const int64_t av = hA[(size_t)i * n + c];
-        if (av <= -((int64_t)1 << 31) || av >= ((int64_t)1 << 31))
-          return set_error(GRAVER_E_OVERFLOW, "|A_ij| must be below 2^31");
-        if (av != 0) {
-          j.csr_col.push_back(c);
-          j.csr_val.push_back(av);
-        }
-      }
-      j.csr_rp[i + 1] = (int32_t)j.csr_col.size();
-    }
+    if ((st = build_csr(hA, m, n, j.csr_rp, j.csr_col, j.csr_val)) != GRAVER_OK) return st;
     if ((st = copy_to_host(ctx, hB, prob->B, (size_t)n * d)) != GRAVER_OK) return st;
     for (int i = 0; i < m; ++i)
       for (int c = 0; c < d; ++c) {
@@ -471,23 +513,10 @@ graver_status job_finish(graver_ctx* ctx, Job& j, int64_t* count_out) {
   j.stt.unique = count;
   {
     EventTimer tm(s);
-    unsigned int* bad = (unsigned int*)W(ctx, j, WS_FLAGS, 64, &st);
-    if (!bad) return st;
-    const int m = j.m;
-    const size_t nnz = j.csr_col.size();
-    const size_t ints = ((size_t)m + 1 + nnz + 1) / 2 * 2;  // int32 part, padded to 8 bytes
-    auto* csr = (int32_t*)W(ctx, j, WS_V_CSR, ints * 4 + std::max<size_t>(nnz, 1) * 8, &st);
-    if (!csr) return st;
-    HIP_TRY(hipMemcpyAsync(csr, j.csr_rp.data(), j.csr_rp.size() * 4, hipMemcpyHostToDevice, s), "csr");
-    if (nnz) {
-      HIP_TRY(hipMemcpyAsync(csr + m + 1, j.csr_col.data(), nnz * 4, hipMemcpyHostToDevice, s), "csr");
-      HIP_TRY(hipMemcpyAsync(csr + ints, j.csr_val.data(), nnz * 8, hipMemcpyHostToDevice, s), "csr");
-    }
-    HIP_TRY(launch_verify(s, j.pool, count, m, (int64_t)nnz, csr, csr + m + 1,
-                          reinterpret_cast<const int64_t*>(csr + ints), bad),
-            "verify");
     unsigned int hbad = 0;
-    HIP_TRY(hipMemcpyAsync(&hbad, bad, sizeof(hbad), hipMemcpyDeviceToHost, s), "verify flag");
+    if ((st = verify_rows(ctx, *j.ws, j.m, j.csr_rp, j.csr_col, j.csr_val, j.pool.keys, j.n, j.pool.stride, count,
+                          &hbad)) != GRAVER_OK)
+      return st;
     j.stt.ms_verify = tm.stop_ms();
     if (hbad) return set_error(GRAVER_E_NOT_KERNEL, "a collected candidate fails A g = 0");
     j.stt.verified = count;
@@ -547,6 +576,36 @@ extern "C" graver_status graver_extract(graver_ctx* ctx, const graver_problem* p
   st = job_finish(ctx, j, count_out);
   if (stats && (st == GRAVER_OK || st == GRAVER_E_CAPACITY)) *stats = j.stt;
   return st;
+}
+
+extern "C" graver_status graver_verify(graver_ctx* ctx, int32_t m, int32_t n, const int64_t* A, const int8_t* keys,
+                                       int64_t count, int64_t* n_bad) {
+  if (!ctx || !A) return set_error(GRAVER_E_INVALID, "NULL argument");
+  if (m < 1 || n < 1 || n > 4096 || count < 0 || count > ((int64_t)1 << 31) - 1024)
+    return set_error(GRAVER_E_INVALID, "bad m, n or count");
+  if (count > 0 && !keys) return set_error(GRAVER_E_INVALID, "keys is NULL");
+  HIP_TRY(hipSetDevice(ctx->device), "set device");
+  graver_status st = GRAVER_OK;
+  std::vector<int64_t> hA;
+  std::vector<int32_t> rp, col;
+  std::vector<int64_t> val;
+  if ((st = copy_to_host(ctx, hA, A, (size_t)m * n)) != GRAVER_OK) return st;
+  if ((st = build_csr(hA, m, n, rp, col, val)) != GRAVER_OK) return st;
+  // rows restrided to the verification kernels' layout (multiple of 16 bytes)
+  const int stride = key_stride(n);
+  int8_t* rows = (int8_t*)ws_get(ctx, WS_KEYSCRATCH, (size_t)std::max<int64_t>(count, 1) * stride, &st);
+  if (!rows) return st;
+  if (count)
+    HIP_TRY(hipMemcpy2DAsync(rows, stride, keys, n, n, (size_t)count, hipMemcpyDeviceToDevice, ctx->stream),
+            "restride keys");
+  unsigned int hbad = 0;
+  if ((st = verify_rows(ctx, ctx->ws, m, rp, col, val, rows, n, stride, (uint32_t)count, &hbad)) != GRAVER_OK)
+    return st;
+  if (n_bad) *n_bad = hbad;
+  if (hbad)
+    return set_error(GRAVER_E_NOT_KERNEL, std::to_string(hbad) + " of " + std::to_string(count) +
+                                              " rows fail A g = 0");
+  return GRAVER_OK;
 }
 
 extern "C" graver_status graver_extract_batch(graver_ctx* ctx, int32_t count, const graver_problem* probs,

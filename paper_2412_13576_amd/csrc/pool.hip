@@ -169,7 +169,8 @@ __global__ void k_verify(const int8_t* keys, int stride, uint32_t count, int m, 
         for (int p = rp[i]; p < rp[i + 1]; ++p) acc += val[p] * (int64_t)key[col[p]];
         ok &= acc == 0 ? 1 : 0;
       }
-      if (!ok) atomicAdd(bad, 1u);
+      // one count per key (the rows of A are spread over the lanes)
+      if (__ballot(!ok) != 0 && lane == 0) atomicAdd(bad, 1u);
     }
     __syncthreads();
   }

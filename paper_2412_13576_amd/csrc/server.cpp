@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -50,6 +51,7 @@ struct Req {
   std::shared_ptr<BasisEntry> basis;
   size_t footprint = 0;
   bool done = false;
+  std::atomic<bool> cancel{false};  // graver_server_cancel was called before it finished
   graver_result res{};
   std::vector<int64_t> x_best;
 };
@@ -143,8 +145,8 @@ void basis_worker(graver_server* s) {
     std::unique_lock<std::mutex> lk(s->mu);
     r->basis = e;
     r->res.t_ready = now_s(s);
-    if (e->st != GRAVER_OK || e->d < 1) {
-      r->res.status = e->st != GRAVER_OK ? e->st : GRAVER_E_INVALID;
+    if (r->cancel || e->st != GRAVER_OK || e->d < 1) {
+      r->res.status = r->cancel ? GRAVER_E_CANCELLED : e->st != GRAVER_OK ? e->st : GRAVER_E_INVALID;
       r->done = true;
       r->res.t_done = now_s(s);
       --s->unfinished;
@@ -367,9 +369,10 @@ void gpu_worker(graver_server* s) {
           }
           if (st == GRAVER_OK) {
             r.res.unique = L.count;
-            st = finish_request(ctx, L, db);
+            // a request cancelled while its extraction ran skips the rest
+            st = r.cancel ? GRAVER_E_CANCELLED : finish_request(ctx, L, db);
           }
-          r.res.status = st;
+          r.res.status = r.cancel ? GRAVER_E_CANCELLED : st;
         }
       } else {
         for (auto& r : batch) r->res.status = bst;
@@ -472,6 +475,51 @@ extern "C" graver_status graver_server_wait(graver_server* s, int64_t ticket, gr
   *res = r->res;
   if (x_best && !r->x_best.empty()) std::memcpy(x_best, r->x_best.data(), r->x_best.size() * sizeof(int64_t));
   s->all.erase(it);
+  return GRAVER_OK;
+}
+
+extern "C" graver_status graver_server_poll(graver_server* s, int64_t ticket, int32_t* done, graver_result* res,
+                                            int64_t* x_best) {
+  if (!s || !done || !res) return set_error(GRAVER_E_INVALID, "NULL argument");
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->all.find(ticket);
+  if (it == s->all.end()) return set_error(GRAVER_E_INVALID, "unknown ticket");
+  std::shared_ptr<Req> r = it->second;
+  *done = r->done ? 1 : 0;
+  if (!r->done) return GRAVER_OK;
+  *res = r->res;
+  if (x_best && !r->x_best.empty()) std::memcpy(x_best, r->x_best.data(), r->x_best.size() * sizeof(int64_t));
+  s->all.erase(it);
+  return GRAVER_OK;
+}
+
+extern "C" graver_status graver_server_cancel(graver_server* s, int64_t ticket, int32_t* cancelled) {
+  if (!s || !cancelled) return set_error(GRAVER_E_INVALID, "NULL argument");
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->all.find(ticket);
+  if (it == s->all.end()) return set_error(GRAVER_E_INVALID, "unknown ticket");
+  std::shared_ptr<Req> r = it->second;
+  if (r->done) {
+    *cancelled = 0;
+    return GRAVER_OK;
+  }
+  r->cancel = true;
+  *cancelled = 1;
+  // still waiting for a basis worker or for admission: it holds no device
+  // memory, so it leaves its queue and finishes now; otherwise the worker
+  // that holds it ends it at its next stage boundary
+  for (auto* q : {&s->queued, &s->ready}) {
+    auto qi = std::find(q->begin(), q->end(), r);
+    if (qi == q->end()) continue;
+    q->erase(qi);
+    r->res.status = GRAVER_E_CANCELLED;
+    r->res.t_done = now_s(s);
+    r->done = true;
+    --s->unfinished;
+    s->cv_done.notify_all();
+    s->cv_ready.notify_all();
+    break;
+  }
   return GRAVER_OK;
 }
 

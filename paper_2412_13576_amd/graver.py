@@ -20,15 +20,16 @@ LIB_PATH = os.path.join(HERE, "libgraver.so")
 GRAVER_FP64, GRAVER_FP32, GRAVER_BF16 = 0, 1, 2
 GRAVER_F_QUADRATIC, GRAVER_F_SEPARABLE_POLY = 1, 2
 (GRAVER_OK, GRAVER_E_INVALID, GRAVER_E_INFEASIBLE_START, GRAVER_E_NOT_KERNEL, GRAVER_E_OVERFLOW,
- GRAVER_E_POOL_FULL, GRAVER_E_NOMEM, GRAVER_E_DEVICE, GRAVER_E_CAPACITY) = range(0, -9, -1)
+ GRAVER_E_POOL_FULL, GRAVER_E_NOMEM, GRAVER_E_DEVICE, GRAVER_E_CAPACITY, GRAVER_E_CANCELLED) = range(0, -10, -1)
 STATUS = {0: "OK", -1: "E_INVALID", -2: "E_INFEASIBLE_START", -3: "E_NOT_KERNEL",
-          -4: "E_OVERFLOW", -5: "E_POOL_FULL", -6: "E_NOMEM", -7: "E_DEVICE", -8: "E_CAPACITY"}
+          -4: "E_OVERFLOW", -5: "E_POOL_FULL", -6: "E_NOMEM", -7: "E_DEVICE", -8: "E_CAPACITY",
+          -9: "E_CANCELLED"}
 
-EXPORTED = ["graver_ctx_create", "graver_ctx_destroy", "graver_ctx_set_stream", "graver_last_error",
+EXPORTED = ["graver_ctx_create", "graver_ctx_destroy", "graver_ctx_set_stream", "graver_ctx_trim", "graver_last_error",
             "graver_status_string", "graver_kernel_basis", "graver_extract", "graver_filter",
-            "graver_augment", "graver_init_solutions", "graver_solve", "graver_lift_inequalities",
+            "graver_augment", "graver_verify", "graver_init_solutions", "graver_solve", "graver_lift_inequalities",
             "graver_extract_batch", "graver_server_create", "graver_server_submit", "graver_server_wait",
-            "graver_server_destroy"]
+            "graver_server_poll", "graver_server_cancel", "graver_server_destroy"]
 
 
 class GraverError(RuntimeError):
@@ -146,6 +147,7 @@ def lib():
         L.graver_ctx_destroy.argtypes = [C.c_void_p]
         L.graver_ctx_destroy.restype = None
         L.graver_ctx_set_stream.argtypes = [C.c_void_p, C.c_void_p]
+        L.graver_ctx_trim.argtypes = [C.c_void_p]
         L.graver_last_error.restype = C.c_char_p
         L.graver_status_string.argtypes = [C.c_int]
         L.graver_status_string.restype = C.c_char_p
@@ -159,6 +161,8 @@ def lib():
         L.graver_augment.argtypes = [C.c_void_p, C.POINTER(Problem), C.POINTER(ObjectiveC), C.c_void_p,
                                      C.c_int64, C.c_int32, C.c_void_p, C.POINTER(AugmentParams),
                                      C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]
+        L.graver_verify.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_int64,
+                                    C.POINTER(C.c_int64)]
         L.graver_init_solutions.argtypes = [C.c_void_p, C.POINTER(Problem), C.POINTER(InitParams),
                                             C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                             C.POINTER(C.c_int64)]
@@ -174,12 +178,17 @@ def lib():
         L.graver_server_create.argtypes = [C.POINTER(C.c_void_p), C.POINTER(ServerParams)]
         L.graver_server_submit.argtypes = [C.c_void_p, C.POINTER(RequestC), C.POINTER(C.c_int64)]
         L.graver_server_wait.argtypes = [C.c_void_p, C.c_int64, C.POINTER(ResultC), C.c_void_p]
+        L.graver_server_poll.argtypes = [C.c_void_p, C.c_int64, C.POINTER(C.c_int32), C.POINTER(ResultC),
+                                         C.c_void_p]
+        L.graver_server_cancel.argtypes = [C.c_void_p, C.c_int64, C.POINTER(C.c_int32)]
         L.graver_server_destroy.argtypes = [C.c_void_p]
         L.graver_server_destroy.restype = None
-        for name in ("graver_ctx_create", "graver_ctx_set_stream", "graver_kernel_basis",
-                     "graver_extract", "graver_filter", "graver_augment", "graver_init_solutions",
+        for name in ("graver_ctx_create", "graver_ctx_set_stream", "graver_ctx_trim", "graver_kernel_basis",
+                     "graver_extract", "graver_filter", "graver_augment",
+                     "graver_verify", "graver_init_solutions",
                      "graver_solve", "graver_lift_inequalities", "graver_extract_batch",
-                     "graver_server_create", "graver_server_submit", "graver_server_wait"):
+                     "graver_server_create", "graver_server_submit", "graver_server_wait",
+                     "graver_server_poll", "graver_server_cancel"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -220,6 +229,10 @@ class Context:
 
     def set_stream(self, stream):
         _check(lib().graver_ctx_set_stream(self.h, C.c_void_p(stream.cuda_stream)))
+
+    def trim(self):
+        """graver_ctx_trim: release the context's device workspace."""
+        _check(lib().graver_ctx_trim(self.h))
 
     def close(self):
         if self.h:
@@ -294,6 +307,20 @@ def filter_minimal(ctx: Context, keys, keys_cap=None):
     _check(lib().graver_filter(ctx.h, n, keys.data_ptr() if count else None, count, out.data_ptr(), cap,
                                C.byref(cnt)))
     return out[: cnt.value]
+
+
+def verify(ctx: Context, A, keys):
+    """graver_verify: the number of rows g of keys (int8 device tensor
+    count x n) with A g != 0; A is an int64 device tensor m x n.  Returns
+    (status, n_bad) without raising on GRAVER_E_NOT_KERNEL."""
+    m, n = A.shape
+    keys = keys.contiguous()
+    nb = C.c_int64(-1)
+    st = lib().graver_verify(ctx.h, m, n, A.contiguous().data_ptr(), keys.data_ptr() if keys.shape[0] else None,
+                             keys.shape[0], C.byref(nb))
+    if st not in (0, -3):
+        _check(st)
+    return st, nb.value
 
 
 def objective(kind: str, Q=None, c=None, coef=None, device="cuda"):
@@ -461,6 +488,25 @@ class Server:
         _check(lib().graver_server_wait(self.h, ticket, C.byref(res), x.ctypes.data))
         r = res.as_dict()
         return r, (x if r["status"] == 0 else None)
+
+    def poll(self, ticket):
+        """(done, result dict or None, x_best or None) without blocking."""
+        res = ResultC()
+        n = self.n[ticket]
+        x = np.zeros(n, np.int64)
+        done = C.c_int32(0)
+        _check(lib().graver_server_poll(self.h, ticket, C.byref(done), C.byref(res), x.ctypes.data))
+        if not done.value:
+            return False, None, None
+        self.n.pop(ticket)
+        r = res.as_dict()
+        return True, r, (x if r["status"] == 0 else None)
+
+    def cancel(self, ticket) -> bool:
+        """True when the request will end with GRAVER_E_CANCELLED."""
+        c = C.c_int32(0)
+        _check(lib().graver_server_cancel(self.h, ticket, C.byref(c)))
+        return bool(c.value)
 
     def close(self):
         if self.h:

@@ -102,3 +102,48 @@ def test_server_tiny_budget_and_errors(G):
     _say("server tiny budget", [(r["batch_size"], r["status"]) for r, _ in res], "bad", rb["status"])
     assert all(r["status"] == 0 and r["batch_size"] == 1 for r, _ in res)
     assert rb["status"] == G.GRAVER_E_INFEASIBLE_START and xb is None
+
+
+def test_server_poll_and_cancel(G):
+    """Poll before and after completion; cancel a request still queued for its
+    basis (one basis thread busy with an LLL basis) and one already running
+    on the GPU; the server keeps serving afterwards."""
+    import time
+    srv = G.Server(max_batch=4, gpu_workers=1, host_threads=1)
+    slow = W.identity_block_instance(21, 300, 60)
+    ex = G.extract_params(16 * 300, 100, precision=G.GRAVER_FP32, init_mode=0, seed=21, pool_capacity=1 << 16)
+    ini = G.init_params(4, 50, seed=22, lr=0.05)
+    ta = srv.submit(slow.A, slow.b, slow.l, slow.u, ex, ini, Q=slow.Q, c=slow.c, lll=True,
+                    x_starts=slow.x0[None, :])
+    item_b = _request(G, 23, 40, 8, "fp32", "quad", T=50)
+    tb = _submit(G, srv, item_b)
+    assert srv.cancel(tb)  # the only basis thread is still reducing the first basis
+    done, ra, _ = srv.poll(ta)
+    assert not done
+    rb, xb = srv.wait(tb)
+    _say("cancelled queued", rb["status"], rb["batch_size"])
+    assert rb["status"] == G.GRAVER_E_CANCELLED and xb is None and rb["batch_size"] == 0
+    t0 = time.time()
+    while True:
+        done, ra, xa = srv.poll(ta)
+        if done:
+            break
+        assert time.time() - t0 < 120
+        time.sleep(0.05)
+    assert ra["status"] == 0 and xa is not None
+    srv.n[ta] = slow.n
+    with pytest.raises(G.GraverError):  # released by the poll that returned it
+        srv.cancel(ta)
+    # a long extraction, cancelled while it runs on the GPU
+    exl = G.extract_params(16 * 300, 100000, precision=G.GRAVER_FP32, init_mode=0, seed=24, pool_capacity=1 << 21)
+    tl = srv.submit(slow.A, slow.b, slow.l, slow.u, exl, ini, Q=slow.Q, c=slow.c, lll=True,
+                    x_starts=slow.x0[None, :])
+    time.sleep(0.5)
+    assert srv.cancel(tl)
+    rl, xl = srv.wait(tl)
+    _say("cancelled running", rl["status"], rl["batch_size"], round(rl["t_done"] - rl["t_submit"], 2))
+    assert rl["status"] == G.GRAVER_E_CANCELLED and xl is None
+    # the server still serves
+    rc, xc = srv.wait(_submit(G, srv, _request(G, 25, 60, 12, "fp32", "quad", T=60)))
+    srv.close()
+    assert rc["status"] == 0 and xc is not None
