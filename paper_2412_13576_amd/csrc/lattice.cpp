@@ -171,6 +171,192 @@ void lll(int n, int d, std::vector<std::vector<int64_t>>& b) {
   }
 }
 
+// ---- kernel basis with reduction interleaved in the elimination ---------
+//
+// The unreduced kernel columns of the elimination above have entries of the
+// size of A's maximal minors, which leave int64 for dense enough A.  Here
+// the rows of A are taken one at a time on a basis of the lattice
+// {x in Z^n : A_0 x = ... = A_{i-1} x = 0} (initially the unit vectors):
+// the row's values v = a_i . b_c on the basis vectors are brought to a single
+// nonzero by unimodular column operations (nearest-integer quotients), the
+// vector holding it leaves the basis, and the remaining vectors, a basis of
+// the lattice with row i added (they are unimodular combinations of the old
+// ones with a_i . b = 0), are LLL-reduced before the next row.  The result
+// spans Ker_Z(A) (Theorem 3.2: any basis of that lattice) with short
+// vectors throughout.  Reduction: LLL with a binary64 Gram-Schmidt computed
+// from the exact integer Gram matrix (Schnorr and Euchner, 1994), Lovasz
+// parameter 0.99 and size bound 0.51; every basis operation is exact integer
+// arithmetic, so the basis is a basis of the lattice whatever the rounding.
+
+constexpr int64_t kRedMax = (int64_t)1 << 40;  // entry bound of the reduced path
+constexpr int64_t kRedTrigger = 1 << 12;        // entries beyond this trigger a reduction
+
+struct FpLattice {
+  int n = 0;
+  std::vector<std::vector<int64_t>> b;   // basis vectors (length n)
+  std::vector<std::vector<__int128>> G;  // exact Gram matrix
+  std::vector<std::vector<double>> mu, r;
+
+  static __int128 dot(const std::vector<int64_t>& x, const std::vector<int64_t>& y) {
+    __int128 s = 0;
+    for (size_t t = 0; t < x.size(); ++t) s += (__int128)x[t] * y[t];
+    return s;
+  }
+  void gram_all() {
+    const int k = (int)b.size();
+    G.assign(k, std::vector<__int128>(k));
+    for (int i = 0; i < k; ++i)
+      for (int j = 0; j <= i; ++j) G[i][j] = G[j][i] = dot(b[i], b[j]);
+  }
+  // b[i] -= q b[j], with the Gram matrix kept exact
+  void axpy(int i, int j, int64_t q) {
+    if (q == 0) return;
+    for (int t = 0; t < n; ++t) {
+      const int64_t v = chk_sub(b[i][t], chk_mul(q, b[j][t]));
+      if (v > kRedMax || v < -kRedMax) throw Overflow();
+      b[i][t] = v;
+    }
+    const int k = (int)b.size();
+    const __int128 gii = G[i][i] - 2 * (__int128)q * G[i][j] + (__int128)q * q * G[j][j];
+    for (int l = 0; l < k; ++l)
+      if (l != i) G[i][l] = G[l][i] = G[i][l] - (__int128)q * G[j][l];
+    G[i][i] = gii;
+  }
+  void swap_vec(int i, int j) {
+    std::swap(b[i], b[j]);
+    std::swap(G[i], G[j]);
+    for (auto& row : G) std::swap(row[i], row[j]);
+  }
+  void drop(int i) {  // remove vector i (order of the others kept)
+    b.erase(b.begin() + i);
+    G.erase(G.begin() + i);
+    for (auto& row : G) row.erase(row.begin() + i);
+  }
+  void gso_row(int i) {
+    double* ri = r[i].data();
+    for (int j = 0; j <= i; ++j) {
+      const double* mj = mu[j].data();
+      // four partial sums (the order only moves rounding; exact integer
+      // operations keep the basis a basis)
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      int l = 0;
+      for (; l + 4 <= j; l += 4) {
+        s0 += mj[l] * ri[l];
+        s1 += mj[l + 1] * ri[l + 1];
+        s2 += mj[l + 2] * ri[l + 2];
+        s3 += mj[l + 3] * ri[l + 3];
+      }
+      for (; l < j; ++l) s0 += mj[l] * ri[l];
+      const double v = (double)G[i][j] - ((s0 + s1) + (s2 + s3));
+      ri[j] = v;
+      if (j < i) mu[i][j] = v / r[j][j];
+    }
+  }
+  // LLL from vector `start` on (the vectors before it are assumed reduced)
+  void lll(int start) {
+    const int k = (int)b.size();
+    if (k < 2) return;
+    mu.assign(k, std::vector<double>(k, 0.0));
+    r.assign(k, std::vector<double>(k, 0.0));
+    for (int i = 0; i < std::max(start, 1); ++i) gso_row(i);
+    int kap = std::max(start, 1);
+    const double delta = 0.99, eta = 0.51;
+    int64_t steps = 0;
+    const int64_t cap = 200LL * k * k + 100000;
+    while (kap < k) {
+      if (++steps > cap) break;  // rounding cycles: stop (still a basis)
+      // size reduction, repeated from the exact Gram matrix until no
+      // coefficient exceeds eta (b*_kap and r[kap][kap] do not change)
+      for (int pass = 0; pass < 64; ++pass) {
+        gso_row(kap);
+        bool any = false;
+        for (int j = kap - 1; j >= 0; --j) {
+          const double m = mu[kap][j];
+          if (!(std::fabs(m) > eta)) continue;
+          if (!(std::fabs(m) < 9.0e15)) throw Overflow();
+          const int64_t q = (int64_t)std::nearbyint(m);
+          axpy(kap, j, q);
+          for (int l = 0; l < j; ++l) mu[kap][l] -= (double)q * mu[j][l];
+          mu[kap][j] -= (double)q;
+          any = true;
+        }
+        if (!any) break;
+      }
+      const double m1 = mu[kap][kap - 1];
+      if (delta * r[kap - 1][kap - 1] > r[kap][kap] + m1 * m1 * r[kap - 1][kap - 1]) {
+        swap_vec(kap, kap - 1);
+        kap = std::max(kap - 1, 1);
+        if (kap == 1) gso_row(0);
+      } else {
+        ++kap;
+      }
+    }
+  }
+};
+
+// Kernel basis of A (m x n) by rows with interleaved reduction; returns the
+// basis vectors.
+std::vector<std::vector<int64_t>> kernel_interleaved(int m, int n, const int64_t* A) {
+  FpLattice L;
+  L.n = n;
+  L.b.assign(n, std::vector<int64_t>(n, 0));
+  for (int i = 0; i < n; ++i) L.b[i][i] = 1;
+  L.gram_all();
+  std::vector<int32_t> nzc;
+  std::vector<int64_t> nzv;
+  for (int i = 0; i < m; ++i) {
+    nzc.clear();
+    nzv.clear();
+    for (int j = 0; j < n; ++j)
+      if (A[(size_t)i * n + j] != 0) {
+        nzc.push_back(j);
+        nzv.push_back(A[(size_t)i * n + j]);
+      }
+    const int k = (int)L.b.size();
+    std::vector<int64_t> v(k);
+    for (int c = 0; c < k; ++c) {
+      __int128 s = 0;
+      for (size_t t = 0; t < nzc.size(); ++t) s += (__int128)nzv[t] * L.b[c][nzc[t]];
+      if (s > INT64_MAX / 4 || s < -(INT64_MAX / 4)) throw Overflow();
+      v[c] = (int64_t)s;
+    }
+    // Euclid over the basis vectors: pivot on the smallest |v_c| (ties: the
+    // shortest vector, then the lowest index) until one nonzero remains
+    int piv = -1;
+    for (;;) {
+      piv = -1;
+      for (int c = 0; c < k; ++c) {
+        if (v[c] == 0) continue;
+        if (piv < 0) {
+          piv = c;
+          continue;
+        }
+        const int64_t a = v[c] < 0 ? -v[c] : v[c], bp = v[piv] < 0 ? -v[piv] : v[piv];
+        if (a < bp || (a == bp && L.G[c][c] < L.G[piv][piv])) piv = c;
+      }
+      if (piv < 0) break;
+      bool clean = true;
+      for (int c = 0; c < k; ++c) {
+        if (c == piv || v[c] == 0) continue;
+        const int64_t q = (int64_t)std::llround((long double)v[c] / (long double)v[piv]);
+        L.axpy(c, piv, q);
+        v[c] -= q * v[piv];
+        if (v[c] != 0) clean = false;
+      }
+      if (clean) break;
+    }
+    if (piv < 0) continue;  // a_i depends on earlier rows
+    L.drop(piv);
+    // reduce once the entries have grown (and after the last row)
+    int64_t mx = 0;
+    for (const auto& vec : L.b)
+      for (int64_t x : vec) mx = std::max<int64_t>(mx, x < 0 ? -x : x);
+    if (mx > kRedTrigger) L.lll(0);
+  }
+  L.lll(0);
+  return L.b;
+}
+
 // P = (B^T B)^{-1} B^T by Cholesky of the exact Gram matrix (binary64) and
 // one step of iterative refinement, solving for all n right-hand sides at
 // once (row-major d x n panels, so the inner loops run along contiguous
@@ -255,13 +441,23 @@ void projector(int n, int d, const std::vector<std::vector<int64_t>>& b, double*
 graver_status kernel_basis_host(int32_t m, int32_t n, const int64_t* A, int32_t do_lll,
                                 int64_t* B_out, int32_t* d_out, double* P_out) {
   try {
-    ColMat K(n, n);
-    int r = hnf(m, n, A, K);
-    int d = n - r;
-    std::vector<std::vector<int64_t>> b(d, std::vector<int64_t>(n));
-    for (int c = 0; c < d; ++c)
-      for (int row = 0; row < n; ++row) b[c][row] = K.at(row, r + c);
-    if (do_lll) lll(n, d, b);
+    std::vector<std::vector<int64_t>> b;
+    try {
+      // Lemma 3.1 as stated: the Hermite normal form's kernel columns, then
+      // (optionally) Algorithm 3 in exact arithmetic
+      ColMat K(n, n);
+      int r = hnf(m, n, A, K);
+      int d = n - r;
+      b.assign(d, std::vector<int64_t>(n));
+      for (int c = 0; c < d; ++c)
+        for (int row = 0; row < n; ++row) b[c][row] = K.at(row, r + c);
+      if (do_lll) lll(n, d, b);
+    } catch (const Overflow&) {
+      // its int64 entries overflow: the same lattice with reduction
+      // interleaved (always reduced, whatever do_lll says)
+      b = kernel_interleaved(m, n, A);
+    }
+    const int d = (int)b.size();
     // exact check A B = 0 (Theorem 3.2 relies on it)
     for (int i = 0; i < m; ++i)
       for (int c = 0; c < d; ++c) {

@@ -3,6 +3,7 @@ exports every declared entry point, and its host kernel basis matches the
 oracle bit for bit."""
 import os
 import re
+from fractions import Fraction
 
 import numpy as np
 import pytest
@@ -94,3 +95,44 @@ def test_lift_inequalities_errors():
     with pytest.raises(G.GraverError) as e:
         G.lift_inequalities(inst.A, inst.b, inst.l, inst.u, Gm * (1 << 60), np.array([0]))
     assert e.value.status == G.GRAVER_E_OVERFLOW
+
+
+def _hermite_is_identity(B):
+    """The rows of B (n x d) generate Z^d, i.e. B is primitive: the oracle's
+    Hermite form of the lattice spanned by the rows is the identity."""
+    H = lattice.hnf_kernel_basis(B.T)["H"]
+    d = B.shape[1]
+    return len(H) == d and all(int(H[i][j]) == (1 if i == j else 0) for i in range(d) for j in range(d))
+
+
+@pytest.mark.parametrize("n,m", [(150, 45), (300, 60)])
+def test_iid_sparse_law_basis_spans_the_kernel_lattice(n, m):
+    """The batching law (A iid, 0 w.p. 0.8 else +-1, +-2): the kernel columns
+    of the Hermite normal form of Lemma 3.1 leave int64 (the oracle's, in
+    exact integers, do), so the library reduces while it eliminates.  Its
+    basis must still span Ker_Z(A) (Theorem 3.2): A B = 0, d = n - rank(A),
+    and B primitive, which with A B = 0 and full rank d makes L(B) the whole
+    kernel lattice; its entries stay within the matrix-core descent's limits."""
+    inst = W.sparse_quadratic_instance(4000 + n, n, m)
+    ho = lattice.hnf_kernel_basis(inst.A)
+    assert max(abs(int(x)) for r in ho["B"] for x in r) >= 2 ** 63
+    B, P = G.kernel_basis(inst.A, lll=True)
+    assert B.shape == (n, n - ho["rank"])
+    assert not np.any(inst.A @ B)
+    assert _hermite_is_identity(B)
+    assert np.abs(B).max() <= 256 and np.abs(B).sum(axis=1).max() * 256 < 2 ** 24
+    assert np.allclose(P @ B, np.eye(B.shape[1]), atol=1e-6)  # the start map z = P g
+
+
+def test_iid_sparse_law_basis_is_reduced():
+    """The reduced basis of that path satisfies Appendix A's exchange
+    condition (ii) ||b*_j||^2 <= 2 ||b*_{j+1}||^2 exactly and the size
+    condition (i) up to the reduction's bound |mu_ij| <= 0.51 (checked with
+    the oracle's exact rational Gram-Schmidt)."""
+    inst = W.sparse_quadratic_instance(4150, 150, 45)
+    B, _ = G.kernel_basis(inst.A, lll=True)
+    cols = [[int(B[r][c]) for r in range(B.shape[0])] for c in range(B.shape[1])]
+    mu, nb = lattice.gram_schmidt_exact(cols)
+    d = len(cols)
+    assert all(nb[j] <= 2 * nb[j + 1] for j in range(d - 1))
+    assert all(abs(mu[i][j]) <= Fraction(51, 100) for i in range(d) for j in range(i))
