@@ -30,7 +30,28 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_MFMA = 157.3  # TFLOP/s, MI355X dense FP32 matrix
+PEAK_BF16_MFMA = 2500.0  # TFLOP/s, MI355X dense bf16 matrix
 PEAK_HBM = 8000.0       # GB/s
+
+
+def descent_roofline(n, d, N, T, ms, bf16_iters=0):
+    """Roofline of one descent launch.  Algorithmic work: 4 n d flop per
+    start-iteration, 2 n d for the forward B z and 2 n d for the backward
+    B^T sign(B z).  Each product is priced at the peak of the matrix unit it
+    runs on: the backward on bf16 (exact operands) in every mode, the forward
+    on FP32 except in the bf16 iterations.  `peak` is the resulting
+    time-weighted peak (work / time at peak), `frac` the time at peak over the
+    measured time."""
+    half = 2.0 * n * d * N
+    polish = T - bf16_iters
+    t_peak = (polish * (half / PEAK_FP32_MFMA + half / PEAK_BF16_MFMA) +
+              bf16_iters * 2.0 * half / PEAK_BF16_MFMA) / 1e12
+    flops = 2.0 * half * T
+    t = ms * 1e-3
+    return {"achieved": flops / t / 1e12, "peak": flops / t_peak / 1e12, "frac": t_peak / t,
+            "peak_note": "time-weighted: forward at the FP32 matrix peak 157.3 TFLOP/s "
+                         f"({polish} binary32 iterations) or bf16 2500 TFLOP/s ({bf16_iters} bf16 iterations), "
+                         "backward at the bf16 peak 2500 TFLOP/s"}
 
 # HBM traffic of the descent kernel, from two rocprofv3 --pmc runs
 # (FETCH_SIZE, WRITE_SIZE) scaled by the same counters on a copy of known
@@ -217,10 +238,10 @@ def bench_precision(args):
 
 def bench_batch(args):
     """Batching: 64 instances, n uniform in [50, 500], m = round(U(0.1, 0.3) n),
-    identity-block law [I | C] (C entries 0 w.p. 0.8 else +-1, +-2), 256 n
-    starts each, 1000 iterations, one batched extraction (autotuned tiles,
-    graph-captured rounds), bf16 vs binary32; against the same instances
-    extracted one call at a time."""
+    A iid (0 w.p. 0.8, else +-1, +-2), box [-5, 5], 256 n starts each, 1000
+    iterations, one batched extraction (autotuned tiles, graph-captured
+    rounds), bf16 vs binary32; against the same instances extracted one call
+    at a time.  Host kernel bases (not timed) are reported beside."""
     import torch
 
     from paper_2412_13576_amd import graver as G
@@ -228,8 +249,11 @@ def bench_batch(args):
     rng = np.random.default_rng(4000)
     ns = rng.integers(50, 501, size=64)
     ms = [int(round(rng.uniform(0.1, 0.3) * n)) for n in ns]
-    insts = [W.identity_block_instance(4000 + k, int(n), m) for k, (n, m) in enumerate(zip(ns, ms))]
-    bases = _bases(insts, [False] * len(insts))
+    insts = [W.sparse_quadratic_instance(4000 + k, int(n), m) for k, (n, m) in enumerate(zip(ns, ms))]
+    t_b = time.perf_counter()
+    bases = _bases(insts, [True] * len(insts))
+    basis_s = time.perf_counter() - t_b
+    print(f"[batch] host bases {basis_s:.1f} s", file=sys.stderr, flush=True)
     T = args.iters if args.iters != 2000 else 1000
     probs = [G.DeviceProblem.from_numpy(it.A, it.b, it.l, it.u, B, P) for it, (B, P) in zip(insts, bases)]
     Ns = [256 * it.n for it in insts]
@@ -267,16 +291,17 @@ def bench_batch(args):
     res["fp32_one_call_per_instance"] = {"wall_ms": seq * 1e3, "start_iterations_per_s": total / seq}
     _line("start-iterations/s, 64 instances in one batched extraction (bf16)", res["bf16"]["start_iterations_per_s"],
           "start-iterations/s", 1, 1, res["bf16"]["wall_ms"], "bf16+f32",
-          {"workload": "64 identity-block instances [I|C], n ~ U{50..500}, m = round(U(0.1,0.3) n), "
-                       "C density 0.2 in +-1,+-2, box [-5,5]", "starts": "256 n per instance", "iters": T,
-           "total_start_iterations": total}, batch=res)
+          {"workload": "64 instances, n ~ U{50..500}, m = round(U(0.1,0.3) n), A iid density 0.2 in "
+                       "+-1,+-2, box [-5,5], quadratic f", "starts": "256 n per instance", "iters": T,
+           "total_start_iterations": total}, batch=res, host_basis_s=basis_s)
     ctx.close()
 
 
 def bench_serve(args):
     """Serving: Poisson arrivals at 50 requests/s, n log-uniform in
-    [20, 1000], m = round(0.2 n), identity-block law, quadratic (box [-5,5])
-    or separable quartic objective 50/50, binary32 or bf16 descent 50/50,
+    [20, 1000], m = round(0.2 n), A iid (0 w.p. 0.8, else +-1, +-2), quadratic
+    (box [-5,5]) or separable quartic objective (box [-20,20]) 50/50, binary32
+    or bf16 descent 50/50,
     16 n starts x 500 iterations, 8 initial-solution starts plus the
     instance's feasible point."""
     from paper_2412_13576_amd import graver as G
@@ -288,31 +313,32 @@ def bench_serve(args):
     reqs = []
     for k, n in enumerate(ns):
         m = max(1, int(round(0.2 * n)))
-        inst = W.identity_block_instance(5000 + k, int(n), m)
+        inst = W.sparse_quadratic_instance(5000 + k, int(n), m)
         N = 16 * int(n)
         bf = rng.random() < 0.5
         ex = G.extract_params(N, 500, precision=G.GRAVER_BF16 if bf else G.GRAVER_FP32, init_mode=0, seed=k,
                               pool_capacity=int(N * max(8, 3000 // int(n))), polish_iters=50 if bf else 0)
         ini = G.init_params(8, 200, seed=k + 1, lr=0.05)
+        l, u = inst.l, inst.u
         if rng.random() < 0.5:
             obj = dict(Q=inst.Q, c=inst.c)
         else:
+            l, u = np.full(int(n), -20, np.int64), np.full(int(n), 20, np.int64)  # the quartic law's box
             coef = np.zeros((int(n), 5))
             coef[:, 4] = rng.uniform(0.1, 1.0, int(n))
             coef[:, 3] = rng.standard_normal(int(n))
             coef[:, 2] = rng.standard_normal(int(n))
             obj = dict(coef=coef)
-        reqs.append((inst, ex, ini, obj, N))
+        reqs.append((inst, l, u, ex, ini, obj, N))
     srv = G.Server(hbm_budget=200 << 30, max_batch=32, gpu_workers=2, host_threads=16, autotune=False,
                    use_graph=True, batch_window_us=2000)
     t0 = time.perf_counter()
     tickets = []
-    for (inst, ex, ini, obj, N), at in zip(reqs, arrivals):
+    for (inst, l, u, ex, ini, obj, N), at in zip(reqs, arrivals):
         dt = at - (time.perf_counter() - t0)
         if dt > 0:
             time.sleep(dt)
-        tickets.append(srv.submit(inst.A, inst.b, inst.l, inst.u, ex, ini, lll=inst.n <= 200,
-                                  x_starts=inst.x0[None, :], **obj))
+        tickets.append(srv.submit(inst.A, inst.b, l, u, ex, ini, lll=True, x_starts=inst.x0[None, :], **obj))
     results = [srv.wait(t)[0] for t in tickets]
     el = time.perf_counter() - t0
     srv.close()
@@ -320,11 +346,12 @@ def bench_serve(args):
     lat = np.array([r["t_done"] - r["t_submit"] for r in ok]) * 1e3
     queue = np.array([r["t_admit"] - r["t_ready"] for r in ok]) * 1e3
     prep = np.array([r["t_ready"] - r["t_submit"] for r in ok]) * 1e3
-    iters = sum(N * 500 for (_, _, _, _, N), r in zip(reqs, results) if r["status"] == 0)
+    iters = sum(N * 500 for (*_, N), r in zip(reqs, results) if r["status"] == 0)
     _line("requests/s at Poisson 50 req/s arrivals (p50/p99 solve latency beside)", len(ok) / el, "requests/s", R, 0,
           el * 1e3 / R, "f32|bf16",
-          {"workload": "Poisson 50/s, identity-block [I|C] n log-uniform [20,1000], m = round(0.2 n), quadratic or "
-                       "quartic, fp32 or bf16, 16 n starts x 500 iterations", "requests": R},
+          {"workload": "Poisson 50/s, n log-uniform [20,1000], m = round(0.2 n), A iid density 0.2 in +-1,+-2, "
+                       "quadratic (box [-5,5]) or quartic (box [-20,20]), fp32 or bf16, 16 n starts x 500 "
+                       "iterations", "requests": R},
           latency_ms={"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                       "max": float(lat.max())},
           basis_ms={"p50": float(np.percentile(prep, 50)), "p99": float(np.percentile(prep, 99))},
@@ -459,8 +486,7 @@ def main():
     n_keys = [r[0] for r in recs]
     n_min = [r[1] for r in recs]
     desc_ms = float(np.mean([r[2]["ms_descent"] for r in recs]))
-    flops = 4.0 * n * d * N * T
-    achieved = flops / (desc_ms * 1e-3) / 1e12
+    roof = descent_roofline(n, d, N, T, desc_ms, bf16_iters=0 if args.precision == "fp32" else T - args.polish)
     out = {
         "metric": "start-iterations/s (whole path: extraction + filter + augmentation)",
         "value": N * T * args.steps / el,
@@ -486,10 +512,11 @@ def main():
         "filtered": float(np.mean(n_min)),
         "aug_best_f": float(recs[-1][3][recs[-1][5]].item()),
         "aug_mean_steps": float(recs[-1][4].double().mean().item()),
-        "roofline": {"bound": "mfma", "kernel": "k_descent_f32", "achieved": achieved,
-                     "peak": PEAK_FP32_MFMA, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA,
+        "roofline": {"bound": "mfma", "kernel": "k_descent_f32", "achieved": roof["achieved"],
+                     "peak": roof["peak"], "unit": "TFLOP/s", "frac": roof["frac"],
                      "traffic": _measured_traffic(N, T, args.precision),
-                     "algorithmic": "4*n*d flop per start-iteration (B z forward + B^T sign backward)"},
+                     "algorithmic": "4*n*d flop per start-iteration (B z forward + B^T sign backward)",
+                     "peak_note": roof["peak_note"]},
     }
     if cpu is not None:
         out["cpu_baseline"] = cpu
