@@ -266,6 +266,25 @@ graver_status graver_augment(graver_ctx* ctx, const graver_problem* prob,
                              const graver_augment_params* params, int64_t* x_out,
                              double* f_out, int64_t* steps_out, int32_t* best_out);
 
+/* graver_augment for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, results and errors as graver_augment; the context supplies
+ * the device and the stream.  It calls no hipMalloc / hipFree: its scratch
+ * (start flags, per-start r rows, per-block best moves, the q_g cache, the
+ * value table) is one fixed 64 MiB array per GPU in the library, allocated
+ * with the library's code object and held until the process ends.  Calls
+ * needing more (about 8 S n + 16 S ceil(K / 256) + 8 K + 1024 n bytes) return
+ * GRAVER_E_CAPACITY and do nothing.  l <= u, u - l <= 127 and the symmetry
+ * of Q are checked on the device (GRAVER_E_INVALID).  Every call on one GPU
+ * shares that array: calls that overlap on one GPU (several host threads or
+ * streams) race and must be serialised by the caller; each call
+ * re-initialises what it reads. */
+graver_status graver_augment_noalloc(graver_ctx* ctx, const graver_problem* prob,
+                                     const graver_objective* f, const int8_t* dirs, int64_t K,
+                                     int32_t S, const int64_t* x_starts,
+                                     const graver_augment_params* params, int64_t* x_out,
+                                     double* f_out, int64_t* steps_out, int32_t* best_out);
+
 /* Initial feasible solutions (Section 3.3, eq. init_sol).  From each of S
  * starting points, `iters` Adam steps minimise
  *     ||A x - b||^2 + lambda3 * sum_i (x_i - floor x_i)(ceil x_i - x_i)

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -15,6 +16,27 @@ namespace graver {
 
 static thread_local std::string g_last_error = "no error";
 
+// Device scratch of graver_augment_noalloc: one array per GPU, held until
+// the process ends.  Host code never passes `scratch` itself to a kernel (in
+// host code the name is a host-side stand-in); it uses the device address
+// that hipGetSymbolAddress returns for the current device, looked up once
+// per device when the first context on that device is created.
+constexpr size_t kNoallocScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+constexpr int kMaxDevices = 64;
+static void* g_scratch_dev[kMaxDevices] = {};
+static std::mutex g_scratch_mu;
+
+// Device address of this device's scratch array (device must be current).
+static graver_status scratch_lookup(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_dev[device]) return GRAVER_OK;
+  void* ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) return hip_error(e != hipSuccess ? e : hipErrorInvalidSymbol, "scratch address");
+  g_scratch_dev[device] = ptr;
+  return GRAVER_OK;
+}
 
 graver_status set_error(graver_status s, const std::string& msg) {
   g_last_error = msg;
@@ -120,6 +142,9 @@ graver_status graver_ctx_create(graver_ctx** out, int32_t device) {
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
     return set_error(GRAVER_E_DEVICE, std::string("library is built for gfx950, device is ") +
                                           prop.gcnArchName);
+  if (device >= kMaxDevices) return set_error(GRAVER_E_INVALID, "device ordinal beyond the library's limit");
+  graver_status sst = scratch_lookup(device);
+  if (sst != GRAVER_OK) return sst;
   graver_ctx* c = new graver_ctx();
   c->device = device;
   *out = c;
@@ -221,7 +246,72 @@ graver_status graver_augment(graver_ctx* ctx, const graver_problem* prob, const 
   } else {
     return set_error(GRAVER_E_INVALID, "unknown objective kind");
   }
-  return run_augment(ctx, a, x_starts, x_out, f_out, steps_out, best_out);
+  int w = 1;
+  for (int i = 0; i < a.n; ++i) w = (int)std::max<int64_t>(w, hu[i] - hl[i] + 1);
+  return run_augment(ctx, a, w, x_starts, x_out, f_out, steps_out, best_out);
+}
+
+graver_status graver_augment_noalloc(graver_ctx* ctx, const graver_problem* prob, const graver_objective* f,
+                                     const int8_t* dirs, int64_t K, int32_t S, const int64_t* x_starts,
+                                     const graver_augment_params* params, int64_t* x_out, double* f_out,
+                                     int64_t* steps_out, int32_t* best_out) {
+  if (!ctx || !f || !params || !prob) return set_error(GRAVER_E_INVALID, "NULL argument");
+  if (ctx->device < 0 || ctx->device >= kMaxDevices || !g_scratch_dev[ctx->device])
+    return set_error(GRAVER_E_INVALID, "no scratch address for this context's device");
+  if (prob->m < 1 || prob->n < 1 || prob->n > 4096)
+    return set_error(GRAVER_E_INVALID, "need m >= 1 and 1 <= n <= 4096");
+  if (!prob->A || !prob->b || !prob->l || !prob->u)
+    return set_error(GRAVER_E_INVALID, "A, b, l, u must be device pointers");
+  if (K < 0 || K > ((int64_t)1 << 30) || (K > 0 && !dirs)) return set_error(GRAVER_E_INVALID, "bad dirs");
+  if (S < 1 || !x_starts || !x_out || !f_out || !steps_out)
+    return set_error(GRAVER_E_INVALID, "need S >= 1 and device start/output buffers");
+  if (params->max_steps < 0) return set_error(GRAVER_E_INVALID, "max_steps < 0");
+  if (f->kind == GRAVER_F_QUADRATIC) {
+    if (!f->Q || !f->c) return set_error(GRAVER_E_INVALID, "quadratic objective needs Q and c");
+  } else if (f->kind == GRAVER_F_SEPARABLE_POLY) {
+    if (!f->coef || f->degree < 0 || f->degree > 8)
+      return set_error(GRAVER_E_INVALID, "separable polynomial needs coef and 0 <= degree <= 8");
+  } else {
+    return set_error(GRAVER_E_INVALID, "unknown objective kind");
+  }
+  // every width u - l is at most 127 (checked below), so a value table of
+  // width 128 serves any box
+  const int w = 128;
+  const size_t need = aug_work_bytes(prob->n, S, K, w);
+  if (need > kNoallocScratchBytes)
+    return set_error(GRAVER_E_CAPACITY, "graver_augment_noalloc: the call needs " + std::to_string(need) +
+                                            " bytes of scratch, the limit is " +
+                                            std::to_string(kNoallocScratchBytes));
+  HIP_TRY(hipSetDevice(ctx->device), "set device");
+  hipStream_t s = ctx->stream;
+  AugWork wk = aug_work_carve(g_scratch_dev[ctx->device], prob->n, S, K, w);
+  // bounds and symmetry of Q checked on the device (no host copy of the instance)
+  unsigned int* vflag = wk.flags + 8;
+  HIP_TRY(launch_aug_validate(s, prob->n, prob->l, prob->u, f->kind == GRAVER_F_QUADRATIC ? f->Q : nullptr, vflag),
+          "validate");
+  unsigned int hv = 0;
+  HIP_TRY(hipMemcpyAsync(&hv, vflag, sizeof(hv), hipMemcpyDeviceToHost, s), "validate");
+  HIP_TRY(hipStreamSynchronize(s), "validate");
+  if (hv & 1u) return set_error(GRAVER_E_INVALID, "l <= u violated");
+  if (hv & 2u) return set_error(GRAVER_E_INVALID, "u - l must be <= 127 (int8 keys)");
+  if (hv & 4u) return set_error(GRAVER_E_INVALID, "Q must be symmetric");
+  AugArgs a{};
+  a.n = prob->n;
+  a.m = prob->m;
+  a.S = S;
+  a.K = (int32_t)K;
+  a.A = prob->A;
+  a.b = prob->b;
+  a.l = prob->l;
+  a.u = prob->u;
+  a.kind = f->kind;
+  a.degree = f->degree;
+  a.Q = f->Q;
+  a.c = f->c;
+  a.coef = f->coef;
+  a.dirs = dirs;
+  a.max_steps = params->max_steps;
+  return run_augment_ws(s, a, w, wk, x_starts, x_out, f_out, steps_out, best_out);
 }
 
 graver_status graver_init_solutions(graver_ctx* ctx, const graver_problem* prob,

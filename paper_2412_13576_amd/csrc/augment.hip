@@ -366,50 +366,102 @@ hipError_t launch_gather_rows_i64(hipStream_t s, const int64_t* src, int n, cons
   return hipGetLastError();
 }
 
-graver_status run_augment(graver_ctx* ctx, const AugArgs& a, const int64_t* x_starts, int64_t* x_out,
+size_t aug_work_bytes(int n, int S, int64_t K, int w) {
+  const int nblk = K > 0 ? (int)((K + kEvalThreads - 1) / kEvalThreads) : 1;
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  return al(64) + al((size_t)S * 4 + 64) + al((size_t)S * n * 8) + al((size_t)S * nblk * sizeof(Move)) +
+         al((size_t)(K > 0 ? K : 1) * 8) + al((size_t)n * w * 8) + al(64);
+}
+
+AugWork aug_work_carve(void* base, int n, int S, int64_t K, int w) {
+  const int nblk = K > 0 ? (int)((K + kEvalThreads - 1) / kEvalThreads) : 1;
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  char* p = static_cast<char*>(base);
+  AugWork wk{};
+  wk.flags = reinterpret_cast<unsigned int*>(p);
+  p += al(64);
+  wk.done = reinterpret_cast<uint32_t*>(p);
+  p += al((size_t)S * 4 + 64);
+  wk.R = reinterpret_cast<double*>(p);
+  p += al((size_t)S * n * 8);
+  wk.partial = p;
+  p += al((size_t)S * nblk * sizeof(Move));
+  wk.qg = reinterpret_cast<uint64_t*>(p);
+  p += al((size_t)(K > 0 ? K : 1) * 8);
+  wk.tab = reinterpret_cast<double*>(p);
+  p += al((size_t)n * w * 8);
+  wk.best = reinterpret_cast<int32_t*>(p);
+  return wk;
+}
+
+// Checks done on the device for callers that cannot copy the instance to
+// the host: flag bit 0 when some l_i > u_i, bit 1 when some u_i - l_i > 127,
+// bit 2 when Q (quadratic, may be NULL) is not symmetric.
+__global__ void k_aug_validate(int n, const int64_t* l, const int64_t* u, const double* Q, unsigned int* flag) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned int bits = 0;
+  if (t < n) {
+    if (l[t] > u[t]) bits |= 1u;
+    else if (u[t] - l[t] > 127) bits |= 2u;
+  }
+  if (Q && t < (int64_t)n * n) {
+    const int64_t i = t / n, j = t % n;
+    if (j < i && Q[i * n + j] != Q[j * n + i]) bits |= 4u;
+  }
+  if (bits) atomicOr(flag, bits);
+}
+
+hipError_t launch_aug_validate(hipStream_t s, int n, const int64_t* l, const int64_t* u, const double* Q,
+                               unsigned int* flag) {
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, flag, (size_t)1);
+  const int64_t cnt = Q ? (int64_t)n * n : n;
+  hipLaunchKernelGGL(k_aug_validate, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, n, l, u, Q, flag);
+  return hipGetLastError();
+}
+
+graver_status run_augment(graver_ctx* ctx, const AugArgs& a, int w, const int64_t* x_starts, int64_t* x_out,
                           double* f_out, int64_t* steps_out, int32_t* best_out) {
-  hipStream_t s = ctx->stream;
   graver_status st = GRAVER_OK;
+  void* base = ws_get(ctx, WS_A_R, aug_work_bytes(a.n, a.S, a.K, w), &st);
+  if (!base) return st;
+  return run_augment_ws(ctx->stream, a, w, aug_work_carve(base, a.n, a.S, a.K, w), x_starts, x_out, f_out,
+                        steps_out, best_out);
+}
+
+graver_status run_augment_ws(hipStream_t s, const AugArgs& a, int w, const AugWork& wk, const int64_t* x_starts,
+                             int64_t* x_out, double* f_out, int64_t* steps_out, int32_t* best_out) {
   const int n = a.n, S = a.S, K = a.K;
-  unsigned int* bad = (unsigned int*)ws_get(ctx, WS_FLAGS, 64, &st);
-  uint32_t* done = (uint32_t*)ws_get(ctx, WS_A_DONE, (size_t)S * 4 + 64, &st);
-  double* R = (double*)ws_get(ctx, WS_A_R, (size_t)S * n * 8, &st);
+  unsigned int* bad = wk.flags;
+  uint32_t* done = wk.done;
+  double* R = wk.R;
   const int nblk = K > 0 ? (K + kEvalThreads - 1) / kEvalThreads : 1;
-  Move* partial = (Move*)ws_get(ctx, WS_A_PART, (size_t)S * nblk * sizeof(Move), &st);
-  double* qg = (double*)ws_get(ctx, WS_A_QG, (size_t)(K > 0 ? K : 1) * 8, &st);
-  int32_t* dbest = (int32_t*)ws_get(ctx, WS_MISC, 64, &st);
-  if (!bad || !done || !R || !partial || !qg || !dbest) return st;
+  Move* partial = static_cast<Move*>(wk.partial);
+  uint64_t* qg = wk.qg;
+  int32_t* dbest = wk.best;
 
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, bad, (size_t)16);
   const int64_t checks = (int64_t)S * (a.m + n);
   hipLaunchKernelGGL(k_check_starts, dim3((unsigned)((checks + 255) / 256)), dim3(256), 0, s, n, a.m, S, a.A, a.b,
-                     a.l, a.u,
-                     x_starts, bad);
+                     a.l, a.u, x_starts, bad);
   unsigned int hbad = 0;
   HIP_TRY(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, s), "augment start check");
   hipError_t e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_error(e, "augment start check");
   if (hbad) return set_error(GRAVER_E_INFEASIBLE_START, "a start violates A x = b or l <= x <= u");
 
-  // value table for separable objectives (width = max(u - l) + 1)
-  int w = 1;
-  double* tab = nullptr;
+  // value table for separable objectives: tab[i * w + (v - l_i)] = p_i(v),
+  // w > max(u - l)
+  const double* tab = nullptr;
   if (a.kind == GRAVER_F_SEPARABLE_POLY) {
-    std::vector<int64_t> hl(n), hu(n);
-    HIP_TRY(hipMemcpyAsync(hl.data(), a.l, n * 8, hipMemcpyDeviceToHost, s), "bounds");
-    HIP_TRY(hipMemcpyAsync(hu.data(), a.u, n * 8, hipMemcpyDeviceToHost, s), "bounds");
-    HIP_TRY(hipStreamSynchronize(s), "bounds");
-    for (int i = 0; i < n; ++i) w = (int)std::max<int64_t>(w, hu[i] - hl[i] + 1);
-    tab = (double*)ws_get(ctx, WS_A_TAB, (size_t)n * w * 8, &st);
-    if (!tab) return st;
     hipLaunchKernelGGL(k_poly_table, dim3((n * w + 255) / 256), dim3(256), 0, s, n, a.degree, w, a.coef, a.l,
-                       a.u, tab);
+                       a.u, wk.tab);
+    tab = wk.tab;
   }
   size_t sn = (size_t)S * n;
   hipLaunchKernelGGL(k_copy_i64, dim3((unsigned)((sn + 255) / 256)), dim3(256), 0, s, x_starts, x_out, sn);
   hipLaunchKernelGGL(k_zero_u32, dim3((S + 255) / 256), dim3(256), 0, s, done, (size_t)S);
   hipLaunchKernelGGL(k_zero_i64, dim3((S + 255) / 256), dim3(256), 0, s, steps_out, (size_t)S);
-  if (K > 0) HIP_TRY(launch_fill_u64(s, reinterpret_cast<uint64_t*>(qg), (uint64_t)K, kQgUnset), "q_g cache");
+  if (K > 0) HIP_TRY(launch_fill_u64(s, qg, (uint64_t)K, kQgUnset), "q_g cache");
   // the group's r rows go to LDS next to the slacks while they fit
   const int lds_r = a.kind == GRAVER_F_QUADRATIC && n <= 256 ? 1 : 0;
   const size_t eval_shm = ((size_t)kStartGroup * 2 * n + 15) / 16 * 16 + (lds_r ? (size_t)kStartGroup * n * 8 : 0);
@@ -420,8 +472,7 @@ graver_status run_augment(graver_ctx* ctx, const AugArgs& a, const int64_t* x_st
       hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, active, (size_t)1);
       hipLaunchKernelGGL(k_prepare, dim3((n + 127) / 128, S), dim3(128), 0, s, a, x_out, done, tab, w, R);
       hipLaunchKernelGGL(k_eval, dim3(nblk, (S + kStartGroup - 1) / kStartGroup), dim3(kEvalThreads),
-                         eval_shm, s, a, x_out, done, R, reinterpret_cast<uint64_t*>(qg), tab, w, lds_r,
-                         partial);
+                         eval_shm, s, a, x_out, done, R, qg, tab, w, lds_r, partial);
       hipLaunchKernelGGL(k_pick, dim3(S), dim3(256), 0, s, a, nblk, partial, x_out, done, steps_out, active);
       uint32_t hact = 0;
       HIP_TRY(hipMemcpyAsync(&hact, active, 4, hipMemcpyDeviceToHost, s), "augment step");

@@ -239,7 +239,25 @@ struct AugArgs {
   const int8_t* dirs;
   int64_t max_steps;
 };
-graver_status run_augment(graver_ctx* ctx, const AugArgs& a, const int64_t* x_starts,
+// Device scratch of one augmentation call, carved from one block of
+// aug_work_bytes(n, S, K, w) bytes (w > max(u - l): width of the value table
+// of a separable objective).
+struct AugWork {
+  unsigned int* flags;  // 64 bytes: start check, step activity
+  uint32_t* done;       // S
+  double* R;            // S x n
+  void* partial;        // S x (direction blocks) best moves
+  uint64_t* qg;         // K cached q_g
+  double* tab;          // n x w
+  int32_t* best;        // best start
+};
+size_t aug_work_bytes(int n, int S, int64_t K, int w);
+AugWork aug_work_carve(void* base, int n, int S, int64_t K, int w);
+hipError_t launch_aug_validate(hipStream_t s, int n, const int64_t* l, const int64_t* u, const double* Q,
+                               unsigned int* flag);
+graver_status run_augment(graver_ctx* ctx, const AugArgs& a, int w, const int64_t* x_starts,
                           int64_t* x_out, double* f_out, int64_t* steps_out, int32_t* best_out);
+graver_status run_augment_ws(hipStream_t s, const AugArgs& a, int w, const AugWork& wk, const int64_t* x_starts,
+                             int64_t* x_out, double* f_out, int64_t* steps_out, int32_t* best_out);
 
 }  // namespace graver

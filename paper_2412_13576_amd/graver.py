@@ -27,7 +27,7 @@ STATUS = {0: "OK", -1: "E_INVALID", -2: "E_INFEASIBLE_START", -3: "E_NOT_KERNEL"
 
 EXPORTED = ["graver_ctx_create", "graver_ctx_destroy", "graver_ctx_set_stream", "graver_ctx_trim", "graver_last_error",
             "graver_status_string", "graver_kernel_basis", "graver_extract", "graver_filter",
-            "graver_augment", "graver_verify", "graver_init_solutions", "graver_solve", "graver_lift_inequalities",
+            "graver_augment", "graver_augment_noalloc", "graver_verify", "graver_init_solutions", "graver_solve", "graver_lift_inequalities",
             "graver_extract_batch", "graver_server_create", "graver_server_submit", "graver_server_wait",
             "graver_server_poll", "graver_server_cancel", "graver_server_destroy"]
 
@@ -161,6 +161,7 @@ def lib():
         L.graver_augment.argtypes = [C.c_void_p, C.POINTER(Problem), C.POINTER(ObjectiveC), C.c_void_p,
                                      C.c_int64, C.c_int32, C.c_void_p, C.POINTER(AugmentParams),
                                      C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]
+        L.graver_augment_noalloc.argtypes = L.graver_augment.argtypes
         L.graver_verify.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_int64,
                                     C.POINTER(C.c_int64)]
         L.graver_init_solutions.argtypes = [C.c_void_p, C.POINTER(Problem), C.POINTER(InitParams),
@@ -184,7 +185,7 @@ def lib():
         L.graver_server_destroy.argtypes = [C.c_void_p]
         L.graver_server_destroy.restype = None
         for name in ("graver_ctx_create", "graver_ctx_set_stream", "graver_ctx_trim", "graver_kernel_basis",
-                     "graver_extract", "graver_filter", "graver_augment",
+                     "graver_extract", "graver_filter", "graver_augment", "graver_augment_noalloc",
                      "graver_verify", "graver_init_solutions",
                      "graver_solve", "graver_lift_inequalities", "graver_extract_batch",
                      "graver_server_create", "graver_server_submit", "graver_server_wait",
@@ -334,23 +335,30 @@ def objective(kind: str, Q=None, c=None, coef=None, device="cuda"):
     return (cf,), ObjectiveC(GRAVER_F_SEPARABLE_POLY, int(coef.shape[1]) - 1, None, None, _ptr(cf))
 
 
-def augment(ctx: Context, prob: DeviceProblem, obj, dirs, x_starts, max_steps: int = 10 ** 6):
-    """graver_augment.  obj = the pair returned by objective().  Returns
-    (x_out, f_out, steps_out) device tensors and the best start index."""
+def augment(ctx: Context, prob: DeviceProblem, obj, dirs, x_starts, max_steps: int = 10 ** 6, out=None,
+            noalloc: bool = False):
+    """graver_augment (graver_augment_noalloc with noalloc=True).  obj = the
+    pair returned by objective().  out: optional (x_out, f_out, steps_out)
+    device tensors to write.  Returns (x_out, f_out, steps_out) device tensors
+    and the best start index."""
     import torch
     _, oc = obj
     S, n = x_starts.shape
     x_starts = x_starts.contiguous()
     dirs = dirs.contiguous()
-    x_out = torch.empty_like(x_starts)
-    f_out = torch.empty(S, dtype=torch.float64, device=x_starts.device)
-    steps = torch.empty(S, dtype=torch.int64, device=x_starts.device)
+    if out is None:
+        x_out = torch.empty_like(x_starts)
+        f_out = torch.empty(S, dtype=torch.float64, device=x_starts.device)
+        steps = torch.empty(S, dtype=torch.int64, device=x_starts.device)
+    else:
+        x_out, f_out, steps = out
     best = C.c_int32(-1)
     pc = prob.c()
     prm = AugmentParams(max_steps)
-    _check(lib().graver_augment(ctx.h, C.byref(pc), C.byref(oc), dirs.data_ptr() if dirs.shape[0] else None,
-                                dirs.shape[0], S, x_starts.data_ptr(), C.byref(prm), x_out.data_ptr(),
-                                f_out.data_ptr(), steps.data_ptr(), C.byref(best)))
+    fn = lib().graver_augment_noalloc if noalloc else lib().graver_augment
+    _check(fn(ctx.h, C.byref(pc), C.byref(oc), dirs.data_ptr() if dirs.shape[0] else None,
+              dirs.shape[0], S, x_starts.data_ptr(), C.byref(prm), x_out.data_ptr(),
+              f_out.data_ptr(), steps.data_ptr(), C.byref(best)))
     return x_out, f_out, steps, best.value
 
 
