@@ -9,8 +9,9 @@
 // HBM/L2 straight into LDS while the current one is used).  z and the gradient
 // accumulators stay in registers; m and v are read and written once per
 // iteration in the wave-native layout.  Per row block ib each wave computes
-//   y_ib   = B_ib z      over its own columns (binary32 MFMA, or the bf16
-//                        hi/lo split), summed over the slices through LDS
+//   y_ib   = B_ib z      over its own columns (binary32 MFMA, or the exact
+//                        three-part bf16 split of z), summed over the slices
+//                        through LDS
 //   G     += B_ib^T sign(y_ib)           (exact bf16 operands, fp32 sums)
 //   g_ib   = B_ib r      for the previous iterate r = round(z) (exact bf16
 //                        operands, integer partial sums, summed over slices)
@@ -36,6 +37,8 @@ namespace graver {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef short shortx4 __attribute__((ext_vector_type(4)));
+typedef short shortx8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 namespace {
 
@@ -64,6 +67,18 @@ __device__ __forceinline__ short sign_bf16(float y) {
   return y > 0.f ? (short)0x3F80 : (y < 0.f ? (short)0xBF80 : (short)0);
 }
 __device__ __forceinline__ short int_bf16(float v) { return (short)(__float_as_uint(v) >> 16); }  // |v| <= 256, integer
+
+// v_mfma_f32_16x16x32_bf16 contracts over 32 indices, lane group l/16
+// supplying the same 8 of them for both operands.  Two 16-column blocks run
+// as one instruction: elements 0-3 of a lane carry the indices it holds in
+// the first block and elements 4-7 those of the second, in both operands, so
+// the sum runs over the union of the two blocks.
+__device__ __forceinline__ floatx4 mfma_pair(shortx4 a0, shortx4 a1, shortx4 b0, shortx4 b1, floatx4 c) {
+  const shortx8 a = __builtin_shufflevector(a0, a1, 0, 1, 2, 3, 4, 5, 6, 7);
+  const shortx8 b = __builtin_shufflevector(b0, b1, 0, 1, 2, 3, 4, 5, 6, 7);
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0,
+                                                 0, 0);
+}
 
 __device__ __forceinline__ float xmax4(float x) {
   x = fmaxf(x, __shfl_xor(x, 16, 64));
@@ -171,6 +186,10 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(const BigArgs* _
   __shared__ floatx4 redG[CS > 1 ? kWaves : 1][64];
   __shared__ float xmu[kWaves][16], xcnt[kWaves][16];
   __shared__ int xflag[kWaves][16];
+  // low bf16 parts of z, per lane, in LDS while they fit next to the
+  // double-buffered basis chunks (widest shape: in registers)
+  constexpr bool kLoLds = BF16F && DBPW <= 12;
+  __shared__ shortx4 sLo[kLoLds ? kWaves : 1][kLoLds ? DBPW : 1][64];
 
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int q = lane >> 4, sl = lane & 15;
@@ -279,16 +298,31 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(const BigArgs* _
 #pragma unroll
         for (int r = 0; r < 4; ++r) rp[jb][r] = int_bf16(rintf(z[jb][r]));
     }
-    shortx4 hi[BF16F ? DBPW : 1], lo[BF16F ? DBPW : 1];
+    // bf16 forward: z = hi + mid + lo exactly, each part the next 8 bits of
+    // the binary32 significand (the residues are exact binary32 differences
+    // of numbers within a factor of two, and the last has at most 8
+    // significant bits); products with the integer entries of B are exact and
+    // the sums are binary32
+    // (the low part waits in this lane's LDS slots: registers hold z, hi, mid)
+    shortx4 hi[BF16F ? DBPW : 1], mid[BF16F ? DBPW : 1], rlo[BF16F && !kLoLds ? DBPW : 1];
     if constexpr (BF16F) {
 #pragma unroll
-      for (int jb = 0; jb < DBPW; ++jb)
+      for (int jb = 0; jb < DBPW; ++jb) {
+        shortx4 lo;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          short h = bf16_rne(z[jb][r]);
+          const short h = bf16_rne(z[jb][r]);
+          const float r1 = z[jb][r] - bf16_to_f(h);
+          const short m = bf16_rne(r1);
           hi[jb][r] = h;
-          lo[jb][r] = bf16_rne(z[jb][r] - bf16_to_f(h));
+          mid[jb][r] = m;
+          lo[r] = bf16_rne(r1 - bf16_to_f(m));
         }
+        if constexpr (kLoLds)
+          sLo[wid][jb][lane] = lo;
+        else
+          rlo[jb] = lo;
+      }
     }
     floatx4 G[DBPW];
 #pragma unroll
@@ -311,18 +345,24 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(const BigArgs* _
         // (bounds the number of LDS operands loaded ahead); independent
         // accumulators shorten the dependent MFMA chains
         if constexpr (BF16F) {
-          floatx4 a1 = floatx4{0.f, 0.f, 0.f, 0.f};
+          // column blocks in pairs through the 32-deep instruction, one
+          // accumulator per part
+          floatx4 a1 = floatx4{0.f, 0.f, 0.f, 0.f}, a2 = a1;
 #pragma unroll
           for (int jg = 0; jg < DBPW; jg += 4) {
 #pragma unroll
-            for (int jb = jg; jb < jg + 4; ++jb) {
-              const shortx4 A = FB[jb * 64 + lane];
-              acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, hi[jb], acc, 0, 0, 0);
-              a1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, lo[jb], a1, 0, 0, 0);
+            for (int jb = jg; jb < jg + 4; jb += 2) {
+              const shortx4 A0 = FB[jb * 64 + lane], A1 = FB[(jb + 1) * 64 + lane];
+              acc = mfma_pair(A0, A1, hi[jb], hi[jb + 1], acc);
+              a1 = mfma_pair(A0, A1, mid[jb], mid[jb + 1], a1);
+              if constexpr (kLoLds)
+                a2 = mfma_pair(A0, A1, sLo[wid][jb][lane], sLo[wid][jb + 1][lane], a2);
+              else
+                a2 = mfma_pair(A0, A1, rlo[jb], rlo[jb + 1], a2);
             }
             __builtin_amdgcn_sched_barrier(0);
           }
-          acc += a1;
+          acc += a1 + a2;
         } else {
           floatx4 a4[4] = {acc, acc, acc, acc};
 #pragma unroll
@@ -343,8 +383,8 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(const BigArgs* _
 #pragma unroll
         for (int jg = 0; jg < DBPW; jg += 4) {
 #pragma unroll
-          for (int jb = jg; jb < jg + 4; ++jb)
-            gx = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(FB[jb * 64 + lane], rp[jb], gx, 0, 0, 0);
+          for (int jb = jg; jb < jg + 4; jb += 2)
+            gx = mfma_pair(FB[jb * 64 + lane], FB[(jb + 1) * 64 + lane], rp[jb], rp[jb + 1], gx);
           __builtin_amdgcn_sched_barrier(0);
         }
       }

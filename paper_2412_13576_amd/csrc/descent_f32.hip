@@ -44,6 +44,8 @@ namespace graver {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef short shortx4 __attribute__((ext_vector_type(4)));
+typedef short shortx8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kWavesPerBlock = 4;
 constexpr int kMaxBlk = 8;  // n, d <= 128
@@ -67,7 +69,13 @@ size_t f32_state_floats(int n, int d, int64_t N) {
 
 // FA[(ib*DB + jb)*64 + l] = (B[16ib + l%16][16jb + 4(l/16) + r], r = 0..3)      float
 // FB[(ib*DB + jb)*64 + l] = the same four entries                              bf16
-// BT[(jb*NB + ib)*64 + l] = (B[16ib + 4(l/16) + r][16jb + l%16], r = 0..3)      bf16
+// BT[(jb*NBP + ip)*64 + l] = (B[32ip + 4(l/16) + r][16jb + l%16], r = 0..3,
+//                             then B[32ip + 16 + 4(l/16) + r][16jb + l%16])    8 x bf16
+// (NBP = ceil(NB / 2) pairs of row blocks, rows past n zero).  The backward
+// runs v_mfma_f32_16x16x32_bf16, whose lane group l/16 supplies 8 of the 32
+// contraction indices for both operands: elements 0-3 of a lane carry the
+// rows it holds in the first row block of the pair and elements 4-7 those of
+// the second, in both operands, so one instruction sums over both blocks.
 __device__ __forceinline__ short bf16_bits_exact_int(int64_t v) {
   // v is an integer with |v| <= 256: exactly representable in bf16
   float f = (float)v;
@@ -89,14 +97,16 @@ __global__ void k_pack(int n, int d, int NB, int DB, const int64_t* B, float* FA
       FB[(size_t)t * 4 + r] = bf16_bits_exact_int(b);
     }
   }
-  {
-    int jb = blkid / NB, ib = blkid % NB;
+  const int NBP = (NB + 1) / 2;
+  if (t < DB * NBP * 64) {
+    int jb = blkid / NBP, ip = blkid % NBP;
     int j = 16 * jb + l % 16;
-    for (int r = 0; r < 4; ++r) {
-      int i = 16 * ib + 4 * (l / 16) + r;
-      int64_t b = (i < n && j < d) ? B[(size_t)i * d + j] : 0;
-      BT[(size_t)t * 4 + r] = bf16_bits_exact_int(b);
-    }
+    for (int h = 0; h < 2; ++h)
+      for (int r = 0; r < 4; ++r) {
+        int i = 32 * ip + 16 * h + 4 * (l / 16) + r;
+        int64_t b = (i < n && j < d) ? B[(size_t)i * d + j] : 0;
+        BT[(size_t)t * 8 + 4 * h + r] = bf16_bits_exact_int(b);
+      }
   }
 }
 
@@ -228,7 +238,7 @@ __device__ __forceinline__ void zero_rows(const LogDev& log, uint32_t first, uin
 template <int NB, int DB>
 __global__ __launch_bounds__(64 * kWavesPerBlock, 1) void k_descent_f32(DescentArgs a, const floatx4* __restrict__ FA,
                                                                          const shortx4* __restrict__ FB,
-                                                                         const shortx4* __restrict__ BT,
+                                                                         const shortx8* __restrict__ BT,
                                                                          float* __restrict__ state, PoolDev pool,
                                                                          unsigned long long* counters,
                                                                          float zrange, int64_t per,
@@ -236,16 +246,17 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 1) void k_descent_f32(DescentA
                                                                          const float2* __restrict__ stepf) {
   extern __shared__ __align__(16) unsigned char smem[];
   floatx4* sFA = reinterpret_cast<floatx4*>(smem);
+  constexpr int NBP = (NB + 1) / 2;
   shortx4* sFB = reinterpret_cast<shortx4*>(sFA + NB * DB * 64);
-  shortx4* sBT = sFB + NB * DB * 64;
-  int* sLim = reinterpret_cast<int*>(sBT + NB * DB * 64);
+  shortx8* sBT = reinterpret_cast<shortx8*>(sFB + NB * DB * 64);
+  int* sLim = reinterpret_cast<int*>(sBT + NBP * DB * 64);
   const int stride = pool.stride;
 
   for (int t = threadIdx.x; t < NB * DB * 64; t += blockDim.x) {
     sFA[t] = FA[t];
     sFB[t] = FB[t];
-    sBT[t] = BT[t];
   }
+  for (int t = threadIdx.x; t < NBP * DB * 64; t += blockDim.x) sBT[t] = BT[t];
   for (int i = threadIdx.x; i < 16 * NB; i += blockDim.x)
     sLim[i] = i < a.n ? (int)(a.u[i] - a.l[i]) : 0;
   __syncthreads();
@@ -331,13 +342,17 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 1) void k_descent_f32(DescentA
 #pragma unroll
     for (int jb = 0; jb < DB; ++jb) gacc[jb] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int ib = 0; ib < NB; ++ib) {
-      shortx4 sg;
+    for (int ip = 0; ip < NBP; ++ip) {
+      shortx8 sg;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) sg[r] = sign_bf16(acc[ib][r]);
+      for (int r = 0; r < 4; ++r) {
+        sg[r] = sign_bf16(acc[2 * ip][r]);
+        sg[4 + r] = 2 * ip + 1 < NB ? sign_bf16(acc[2 * ip + 1][r]) : (short)0;
+      }
 #pragma unroll
       for (int jb = 0; jb < DB; ++jb)
-        gacc[jb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(sBT[(jb * NB + ib) * 64 + lane], sg, gacc[jb], 0, 0, 0);
+        gacc[jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, sBT[(jb * NBP + ip) * 64 + lane]),
+                                                           __builtin_bit_cast(bf16x8, sg), gacc[jb], 0, 0, 0);
     }
     __builtin_amdgcn_sched_barrier(0);
     // ---- barrier term: ||z||_inf and ties, per start (4 lanes) ----
@@ -562,14 +577,15 @@ static hipError_t launch_nd(hipStream_t s, const DescentArgs& a, const float* FA
   const int lim_uniform = a.lim_uniform;
   const int64_t nw = n_waves(a.N);
   const int64_t per = nw * 4 * DB * 64;
-  const size_t shmem = (size_t)NB * DB * 64 * (sizeof(floatx4) + 2 * sizeof(shortx4)) + 16 * NB * sizeof(int);
+  const size_t shmem = (size_t)NB * DB * 64 * (sizeof(floatx4) + sizeof(shortx4)) +
+                       (size_t)((NB + 1) / 2) * DB * 64 * sizeof(shortx8) + 16 * NB * sizeof(int);
   auto kern = k_descent_f32<NB, DB>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
   if (e != hipSuccess) return e;
   const size_t nblk64 = (size_t)NB * DB * 64;
   hipLaunchKernelGGL(kern, dim3((unsigned)(nw / kWavesPerBlock)), dim3(64 * kWavesPerBlock), shmem, s, a,
                      reinterpret_cast<const floatx4*>(FA), reinterpret_cast<const shortx4*>(FA + nblk64 * 4),
-                     reinterpret_cast<const shortx4*>(BA), state, pool, counters, zrange, per, lim_uniform,
+                     reinterpret_cast<const shortx8*>(BA), state, pool, counters, zrange, per, lim_uniform,
                      a.log, reinterpret_cast<const float2*>(a.stepf));
   return hipGetLastError();
 }

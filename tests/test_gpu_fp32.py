@@ -337,7 +337,7 @@ def test_precision_forms_recall(G, ctx, qp):
         C = {canonical(r) for r in k.cpu().numpy().tolist()}
         rec[name] = len(C & R) / len(R)
     _say("precision recall", rec, "descent ms", times)
-    assert rec["bf16"] >= rec["fp32"] - 0.05
+    assert rec["bf16"] >= rec["fp32"] - 0.01  # equal recall
 
 
 def test_log_overflow_replay_keeps_every_candidate(G, ctx):

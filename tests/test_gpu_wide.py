@@ -156,3 +156,32 @@ def test_wide_resume_and_overflow_replay(G, ctx, prec):
                       state={"z": _dev(z0)})
     assert torch.equal(kb, ks)
     _say("wide resume / replay", prec, "unique", kb.shape[0], "events", sb["inbox_events"])
+
+
+def test_quartic_precision_forms_equal_recall(G, ctx):
+    """The precision comparison on the quartic workload (n = 400, d = 350):
+    binary32 vs bf16 (last 10% of the steps polished in binary32) from the
+    same 8192 box starts x 2000 steps; each form's recall against the
+    filtered union of both sets.  Equal recall means the bf16 form is within
+    0.01 of the binary32 form."""
+    inst, B = _inst("quartic_n400_d350")
+    P = lattice.coordinate_projector(B)
+    N, T = 8192, 2000
+    prob = G.DeviceProblem.from_numpy(inst.A, inst.b, inst.l, inst.u, B, P)
+    sets, times = {}, {}
+    for name, prec, pol in (("fp32", G.GRAVER_FP32, 0), ("bf16", G.GRAVER_BF16, T // 10)):
+        _say("quartic recall", name)
+        prm = G.extract_params(N, T, precision=prec, init_mode=0, seed=77, polish_iters=pol, pool_capacity=1 << 23,
+                               any_order=True)
+        k, st = G.extract(ctx, prob, prm)
+        sets[name] = G.filter_minimal(ctx, k)
+        times[name] = st["ms_descent"]
+        del k
+    ref = G.filter_minimal(ctx, torch.cat([sets["fp32"], sets["bf16"]]))
+    rv = np.ascontiguousarray(ref.cpu().numpy()).view(np.dtype((np.void, ref.shape[1]))).ravel()
+    rec = {}
+    for name, F in sets.items():
+        fv = np.ascontiguousarray(F.cpu().numpy()).view(np.dtype((np.void, F.shape[1]))).ravel()
+        rec[name] = float(np.isin(rv, fv).sum() / max(1, rv.size))
+    _say("quartic recall", rec, "descent ms", times)
+    assert rec["bf16"] >= rec["fp32"] - 0.01
