@@ -149,15 +149,19 @@ static void scan_exclusive(hipStream_t s, const uint32_t* in, uint32_t* out, uin
 
 // Row movers run a thread per 8-byte word, so the lanes that copy one row
 // read and write whole cache lines.
+// (grid-stride: count rows of stride / 8 words can exceed the 2^32 - 1
+// work-items of one dispatch)
 __global__ void k_compact_rows(const int8_t* src, int stride, const uint32_t* idx, const uint32_t* flag,
                                const uint32_t* pos, uint32_t count, int8_t* dst) {
   const int L = stride / 8;
-  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint64_t i = t / L;
-  const int w = (int)(t - i * L);
-  if (i >= count || !flag[i]) return;
-  const uint64_t* a = reinterpret_cast<const uint64_t*>(src + (size_t)(idx ? idx[i] : (uint32_t)i) * stride);
-  reinterpret_cast<uint64_t*>(dst + (size_t)pos[i] * stride)[w] = a[w];
+  const uint64_t total = (uint64_t)count * L;
+  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t i = t / L;
+    const int w = (int)(t - i * L);
+    if (!flag[i]) continue;
+    const uint64_t* a = reinterpret_cast<const uint64_t*>(src + (size_t)(idx ? idx[i] : (uint32_t)i) * stride);
+    reinterpret_cast<uint64_t*>(dst + (size_t)pos[i] * stride)[w] = a[w];
+  }
 }
 
 // ---- LSD radix sort of 64-bit keys, 4 bits per pass ----------------------
@@ -230,16 +234,18 @@ __global__ void k_scatter_flags(const uint32_t* idx, const uint32_t* alive, uint
 __global__ void k_compact_out(const int8_t* src, int stride, const uint32_t* flag, const uint32_t* pos,
                               uint32_t count, int n, int8_t* out) {
   const int nw = (n + 3) / 4;
-  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint64_t i = t / nw;
-  const int w = (int)(t % nw);
-  if (i >= count || !flag[i]) return;
-  const int8_t* a = src + (size_t)i * stride + 4 * w;
-  int8_t* b = out + (size_t)pos[i] * n + 4 * w;
-  if ((n & 3) == 0) {
-    *reinterpret_cast<uint32_t*>(b) = *reinterpret_cast<const uint32_t*>(a);
-  } else {
-    for (int j = 0; j < 4 && 4 * w + j < n; ++j) b[j] = a[j];
+  const uint64_t total = (uint64_t)count * nw;
+  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t i = t / nw;
+    const int w = (int)(t % nw);
+    if (!flag[i]) continue;
+    const int8_t* a = src + (size_t)i * stride + 4 * w;
+    int8_t* b = out + (size_t)pos[i] * n + 4 * w;
+    if ((n & 3) == 0) {
+      *reinterpret_cast<uint32_t*>(b) = *reinterpret_cast<const uint32_t*>(a);
+    } else {
+      for (int j = 0; j < 4 && 4 * w + j < n; ++j) b[j] = a[j];
+    }
   }
 }
 
@@ -294,14 +300,16 @@ __global__ void k_gather_rows(const int8_t* src, int stride, const uint32_t* idx
                               int8_t* dst, const int32_t* l1src, int32_t* l1dst, const uint64_t* msrc,
                               uint64_t* mdst, int W) {
   const int L = stride / 8;
-  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint64_t i = t / L;
-  const int w = (int)(t - i * L);
-  if (i >= count) return;
-  const uint32_t j = idx[i];
-  reinterpret_cast<uint64_t*>(dst + (size_t)i * stride)[w] = reinterpret_cast<const uint64_t*>(src + (size_t)j * stride)[w];
-  if (w == 0) l1dst[i] = l1src[j];
-  if (w < 2 * W) mdst[(size_t)i * 2 * W + w] = msrc[(size_t)j * 2 * W + w];
+  const uint64_t total = (uint64_t)count * L;
+  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t i = t / L;
+    const int w = (int)(t - i * L);
+    const uint32_t j = idx[i];
+    reinterpret_cast<uint64_t*>(dst + (size_t)i * stride)[w] =
+        reinterpret_cast<const uint64_t*>(src + (size_t)j * stride)[w];
+    if (w == 0) l1dst[i] = l1src[j];
+    if (w < 2 * W) mdst[(size_t)i * 2 * W + w] = msrc[(size_t)j * 2 * W + w];
+  }
 }
 
 // lo[p] = first position whose l1 equals l1[p] (l1 sorted ascending).
@@ -380,11 +388,12 @@ __global__ __launch_bounds__(kTileRows) void k_codes(const int8_t* keys, int str
 
 // masks in bucket order: bmask row e = mask row bl[e] (a thread per word)
 __global__ void k_bucket_masks(const uint32_t* bl, const uint64_t* mask, uint32_t count, int W, uint64_t* bmask) {
-  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint64_t e = t / (2 * W);
-  const int w = (int)(t - e * 2 * W);
-  if (e >= count) return;
-  bmask[e * 2 * W + w] = mask[(size_t)bl[e] * 2 * W + w];
+  const uint64_t total = (uint64_t)count * 2 * W;
+  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t e = t / (2 * W);
+    const int w = (int)(t - e * 2 * W);
+    bmask[e * 2 * W + w] = mask[(size_t)bl[e] * 2 * W + w];
+  }
 }
 
 __global__ void k_bucket_scatter(const uint32_t* code, uint32_t count, const uint32_t* off, uint32_t* cur,
@@ -587,10 +596,12 @@ hipError_t launch_filter(hipStream_t s, graver_ctx* ctx, int n, const int8_t* in
   const int trows = tile_rows_for(stride);
   hipLaunchKernelGGL(k_canon, dim3((cnt + trows - 1) / trows), dim3(kTileRows), (size_t)trows * stride, s, in,
                      (int64_t)cnt, n, stride, trows, canon);
+  HIP_RET(hipGetLastError());
   uint64_t* spk = (uint64_t*)ws_get(ctx, WS_SORT_TMP, (size_t)p2 * 8, st);
   if (!spk) return hipSuccess;
   HIP_RET(launch_sort_keys(s, canon, stride, cnt, idx, spk));
   hipLaunchKernelGGL(k_mark_unique, dim3(b256), dim3(256), 0, s, canon, stride, idx, spk, cnt, flag);
+  HIP_RET(hipGetLastError());
   scan_exclusive(s, flag, pos, cnt, scr);
   uint32_t hlast[2] = {0, 0};
   HIP_RET(hipMemcpyAsync(&hlast[0], pos + cnt - 1, 4, hipMemcpyDeviceToHost, s));
@@ -600,13 +611,15 @@ hipError_t launch_filter(hipStream_t s, graver_ctx* ctx, int n, const int8_t* in
   const uint32_t U = hlast[0] + hlast[1];
   if (U == 0) return hipSuccess;
   const uint64_t rw = (uint64_t)stride / 8;
-  hipLaunchKernelGGL(k_compact_rows, dim3((unsigned)((cnt * rw + 255) / 256)), dim3(256), 0, s, canon, stride, idx,
+  hipLaunchKernelGGL(k_compact_rows, dim3(stride_grid((uint64_t)cnt * rw)), dim3(256), 0, s, canon, stride, idx,
                      flag, pos, cnt, uniq);
+  HIP_RET(hipGetLastError());
   const unsigned u256 = (U + 255) / 256;
   int32_t* l1b = l1 + cnt;
   uint64_t* mskb = msk + (size_t)cnt * 2 * W;
   hipLaunchKernelGGL(k_prep, dim3((U + trows - 1) / trows), dim3(kTileRows), (size_t)trows * stride, s, uniq, stride,
                      n, U, W, trows, l1, msk);
+  HIP_RET(hipGetLastError());
   // (l1, lex) order: uniq is lexicographic, so sorting the distinct keys
   // (l1 << bits_pos) | lex position is a stable reorder by l1
   {
@@ -619,13 +632,17 @@ hipError_t launch_filter(hipStream_t s, graver_ctx* ctx, int n, const int8_t* in
     uint32_t* rh = (uint32_t*)ws_get(ctx, WS_R_HIST, (size_t)nblocks * 16 * 4 * 2 + 64, st);
     if (!rk || !rh) return hipSuccess;
     hipLaunchKernelGGL(k_l1_keys, dim3(u256), dim3(256), 0, s, l1, U, bits_pos, rk);
+    HIP_RET(hipGetLastError());
     uint64_t* sorted = radix_sort_u64(s, rk, rk + U, U, bits_l1 + bits_pos, rh, rh + (size_t)nblocks * 16, scr);
     hipLaunchKernelGGL(k_low_bits, dim3(u256), dim3(256), 0, s, sorted, U, bits_pos, idx);
+    HIP_RET(hipGetLastError());
   }
-  hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)((U * rw + 255) / 256)), dim3(256), 0, s, uniq, stride, idx, U,
+  hipLaunchKernelGGL(k_gather_rows, dim3(stride_grid((uint64_t)U * rw)), dim3(256), 0, s, uniq, stride, idx, U,
                      canon, l1, l1b,
                      msk, mskb, W);
+  HIP_RET(hipGetLastError());
   hipLaunchKernelGGL(k_level_start, dim3(u256), dim3(256), 0, s, l1b, U, lo);
+  HIP_RET(hipGetLastError());
   // sign-pattern index on the k most frequently nonzero coordinates
   Coords C{};
   {
@@ -642,9 +659,11 @@ hipError_t launch_filter(hipStream_t s, graver_ctx* ctx, int n, const int8_t* in
       uint32_t* cnt = (uint32_t*)ws_get(ctx, WS_F_CODE, ((size_t)U + n + 64) * 4, st);
       if (!cnt) return hipSuccess;
       hipLaunchKernelGGL(k_zero32, dim3((n + 255) / 256), dim3(256), 0, s, cnt, (uint32_t)n);
+      HIP_RET(hipGetLastError());
       const uint32_t step = (U + kNnzSampleRows - 1) / kNnzSampleRows;
       const uint32_t rows = (U + step - 1) / step;
       hipLaunchKernelGGL(k_col_nnz, dim3((rows + 63) / 64), dim3(128), 0, s, canon, stride, n, rows, step, cnt);
+      HIP_RET(hipGetLastError());
       HIP_RET(hipMemcpyAsync(hc.data(), cnt, (size_t)n * 4, hipMemcpyDeviceToHost, s));
       e = hipStreamSynchronize(s);
       if (e != hipSuccess) return e;
@@ -671,16 +690,21 @@ hipError_t launch_filter(hipStream_t s, graver_ctx* ctx, int n, const int8_t* in
   if (!code || !hist || !boff || !cur || !bl || !scr2) return hipSuccess;
   const unsigned c256 = (ncode + 1 + 255) / 256;
   hipLaunchKernelGGL(k_zero32, dim3(c256), dim3(256), 0, s, hist, ncode + 1);
+  HIP_RET(hipGetLastError());
   hipLaunchKernelGGL(k_zero32, dim3(c256), dim3(256), 0, s, cur, ncode + 1);
+  HIP_RET(hipGetLastError());
   hipLaunchKernelGGL(k_codes, dim3((U + trows - 1) / trows), dim3(kTileRows), (size_t)trows * stride, s, canon, stride,
                      U, C, trows, code, hist);
+  HIP_RET(hipGetLastError());
   scan_exclusive(s, hist, boff, ncode + 1, scr2);
   hipLaunchKernelGGL(k_bucket_scatter, dim3(u256), dim3(256), 0, s, code, U, boff, cur, bl);
+  HIP_RET(hipGetLastError());
   // the masks in bucket order go to the first half of the mask buffer (its
   // lexicographic-order masks are no longer read)
   uint64_t* bmsk = msk;
-  hipLaunchKernelGGL(k_bucket_masks, dim3((unsigned)(((uint64_t)U * 2 * W + 255) / 256)), dim3(256), 0, s, bl, mskb, U,
+  hipLaunchKernelGGL(k_bucket_masks, dim3(stride_grid((uint64_t)U * 2 * W)), dim3(256), 0, s, bl, mskb, U,
                      W, bmsk);
+  HIP_RET(hipGetLastError());
   // join work items: chunks of at most kJoinThreads members of one bucket
   const size_t max_items = (size_t)(U < ncode ? U : ncode) + U / kJoinThreads + 1;
   uint32_t* chk = (uint32_t*)ws_get(ctx, WS_F_CHUNK, ((size_t)2 * (ncode + 1) + max_items + 64) * 4, st);
@@ -689,15 +713,19 @@ hipError_t launch_filter(hipStream_t s, graver_ctx* ctx, int n, const int8_t* in
   uint32_t* choff = chk + (ncode + 1);
   uint32_t* owner = chk + 2 * (size_t)(ncode + 1);
   hipLaunchKernelGGL(k_chunk_count, dim3(c256), dim3(256), 0, s, hist, ncode, nch);
+  HIP_RET(hipGetLastError());
   scan_exclusive(s, nch, choff, ncode + 1, scr2);
   hipLaunchKernelGGL(k_chunk_owner, dim3((ncode + 255) / 256), dim3(256), 0, s, nch, choff, ncode, owner);
+  HIP_RET(hipGetLastError());
   const int tile_n = W <= 4 ? 256 : (W <= 16 ? 64 : 16);
   const size_t jshm = (size_t)tile_n * (2 * W * sizeof(uint64_t) + sizeof(uint32_t));
   const unsigned jgrid = (unsigned)(max_items < (1u << 20) ? max_items : (1u << 20));
   hipLaunchKernelGGL(k_pairs_join, dim3(jgrid), dim3(kJoinThreads), jshm, s, canon, stride, n, W, mskb, lo, boff, bl,
                      bmsk, C, choff, owner, ncode, tile_n, alive);
+  HIP_RET(hipGetLastError());
   // survivors back in lexicographic order: flags to lex positions, then compact uniq
   hipLaunchKernelGGL(k_scatter_flags, dim3(u256), dim3(256), 0, s, idx, alive, U, flag);
+  HIP_RET(hipGetLastError());
   scan_exclusive(s, flag, pos, U, scr);
   HIP_RET(hipMemcpyAsync(&hlast[0], pos + U - 1, 4, hipMemcpyDeviceToHost, s));
   HIP_RET(hipMemcpyAsync(&hlast[1], flag + U - 1, 4, hipMemcpyDeviceToHost, s));
@@ -710,8 +738,9 @@ hipError_t launch_filter(hipStream_t s, graver_ctx* ctx, int n, const int8_t* in
     return hipSuccess;
   }
   const uint64_t words = (uint64_t)U * ((n + 3) / 4);
-  hipLaunchKernelGGL(k_compact_out, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, s, uniq, stride, flag, pos,
+  hipLaunchKernelGGL(k_compact_out, dim3(stride_grid(words)), dim3(256), 0, s, uniq, stride, flag, pos,
                      U, n, out);
+  HIP_RET(hipGetLastError());
   return hipStreamSynchronize(s);
 }
 

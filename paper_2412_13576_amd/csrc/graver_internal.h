@@ -8,6 +8,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "graver.h"
 
 namespace graver {
@@ -55,6 +57,15 @@ graver_status copy_to_host(graver_ctx* ctx, std::vector<T>& dst, const T* src, s
   HIP_TRY(hipStreamSynchronize(ctx->stream), "stream synchronize");
   return GRAVER_OK;
 }
+
+// A named phase on rocprofv3's marker trace (--marker-trace) for the
+// lifetime of the object (a roctx range; free when no tool is attached).
+struct Phase {
+  explicit Phase(const char* name) { roctxRangePushA(name); }
+  ~Phase() { roctxRangePop(); }
+  Phase(const Phase&) = delete;
+  Phase& operator=(const Phase&) = delete;
+};
 
 // Device time between construction and stop_ms() on one stream.
 struct EventTimer {
@@ -126,6 +137,14 @@ struct LogDev {
 
 // Counters written by the descent kernels (atomic adds, int64).
 enum Counter : int { C_EMIT = 0, C_INBOX, C_RANGE, C_NCOUNTERS };
+
+// Blocks of 256 threads for a grid-stride loop over `threads` items: a
+// dispatch counts at most 2^32 - 1 work-items, so the grid is capped at
+// 2^22 blocks (2^30 threads) and each thread loops.
+inline unsigned stride_grid(uint64_t threads) {
+  const uint64_t b = (threads + 255) / 256;
+  return (unsigned)(b < ((uint64_t)1 << 22) ? (b > 0 ? b : 1) : ((uint64_t)1 << 22));
+}
 
 // ---- launchers (implemented in the .hip files) --------------------------
 struct DescentArgs {

@@ -324,22 +324,23 @@ hipError_t launch_sort_keys(hipStream_t s, const int8_t* keys, int stride, uint3
   return hipGetLastError();
 }
 
+// a thread per byte, grid-stride (a dispatch counts at most 2^32 - 1 work-items)
 __global__ void k_gather(const int8_t* keys, int stride, int n, const uint32_t* idx, uint32_t count,
                          int8_t* out, int out_stride) {
-  uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  uint64_t total = (uint64_t)count * n;
-  if (t >= total) return;
-  uint32_t r = (uint32_t)(t / n);
-  int c = (int)(t % n);
-  out[(size_t)r * out_stride + c] = keys[(size_t)idx[r] * stride + c];
+  const uint64_t total = (uint64_t)count * n;
+  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t r = (uint32_t)(t / n);
+    const int c = (int)(t % n);
+    out[(size_t)r * out_stride + c] = keys[(size_t)idx[r] * stride + c];
+  }
 }
 
 hipError_t launch_gather_keys(hipStream_t s, const int8_t* keys, int stride, int n,
                               const uint32_t* idx, uint32_t count, int8_t* out, int out_stride) {
   uint64_t total = (uint64_t)count * n;
   if (total == 0) return hipGetLastError();
-  hipLaunchKernelGGL(k_gather, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, keys, stride,
-                     n, idx, count, out, out_stride);
+  hipLaunchKernelGGL(k_gather, dim3(stride_grid(total)), dim3(256), 0, s, keys, stride, n, idx, count, out,
+                     out_stride);
   return hipGetLastError();
 }
 
