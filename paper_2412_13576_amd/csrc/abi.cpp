@@ -183,6 +183,7 @@ graver_status graver_ctx_set_stream(graver_ctx* ctx, void* hip_stream) {
 
 graver_status graver_kernel_basis(int32_t m, int32_t n, const int64_t* A, int32_t lll,
                                   int64_t* B_out, int32_t* d_out, double* P_out) {
+  Phase ph("graver_kernel_basis (host)");
   if (m < 1 || n < 1 || n > 4096 || !A || !B_out || !d_out)
     return set_error(GRAVER_E_INVALID, "graver_kernel_basis: bad arguments");
   return kernel_basis_host(m, n, A, lll, B_out, d_out, P_out);
@@ -196,6 +197,7 @@ graver_status graver_filter(graver_ctx* ctx, int32_t n, const int8_t* keys_in, i
   if (count_in > 0 && !keys_in) return set_error(GRAVER_E_INVALID, "keys_in is NULL");
   if (keys_cap < 0 || (keys_cap > 0 && !keys_out)) return set_error(GRAVER_E_INVALID, "bad output buffer");
   HIP_TRY(hipSetDevice(ctx->device), "set device");
+  Phase ph("graver_filter (dedup, minimality)");
   graver_status st = GRAVER_OK;
   hipError_t e = launch_filter(ctx->stream, ctx, n, keys_in, count_in, keys_out, keys_cap, count_out, &st);
   if (st != GRAVER_OK) return st;
@@ -209,6 +211,7 @@ graver_status graver_augment(graver_ctx* ctx, const graver_problem* prob, const 
                              int64_t* steps_out, int32_t* best_out) {
   if (!ctx || !f || !params) return set_error(GRAVER_E_INVALID, "NULL argument");
   HIP_TRY(hipSetDevice(ctx->device), "set device");
+  Phase ph("graver_augment (Algorithm 1)");
   std::vector<int64_t> hl, hu;
   graver_status st = validate_problem(ctx, prob, true, hl, hu);
   if (st != GRAVER_OK) return st;
@@ -320,6 +323,7 @@ graver_status graver_init_solutions(graver_ctx* ctx, const graver_problem* prob,
                                     int64_t* n_feasible) {
   if (!ctx || !prm || !sol_out || !feasible_out) return set_error(GRAVER_E_INVALID, "NULL argument");
   HIP_TRY(hipSetDevice(ctx->device), "set device");
+  Phase ph("graver_init_solutions (eq. init_sol)");
   if (!prob) return set_error(GRAVER_E_INVALID, "problem is NULL");
   if (prob->m < 1 || prob->n < 1 || prob->n > 4096)
     return set_error(GRAVER_E_INVALID, "need m >= 1 and 1 <= n <= 4096");

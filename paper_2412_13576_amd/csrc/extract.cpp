@@ -563,6 +563,7 @@ extern "C" graver_status graver_extract(graver_ctx* ctx, const graver_problem* p
                                         graver_extract_stats* stats) {
   if (!ctx || !prm || !count_out) return set_error(GRAVER_E_INVALID, "NULL argument");
   HIP_TRY(hipSetDevice(ctx->device), "set device");
+  Phase ph("graver_extract");
   Job j;
   j.prob = prob;
   j.prm = prm;
@@ -570,10 +571,21 @@ extern "C" graver_status graver_extract(graver_ctx* ctx, const graver_problem* p
   j.keys_out = keys_out;
   j.keys_cap = keys_cap;
   j.ws = &ctx->ws;
-  graver_status st = job_setup(ctx, j, false, false);
+  graver_status st;
+  {
+    Phase p1("extract: setup (validation, starts, pool)");
+    st = job_setup(ctx, j, false, false);
+  }
   if (st != GRAVER_OK) return st;
-  if ((st = job_descend(ctx, j, j.T)) != GRAVER_OK) return st;
-  st = job_finish(ctx, j, count_out);
+  {
+    Phase p2("extract: descent and collection (Algorithm 2)");
+    st = job_descend(ctx, j, j.T);
+  }
+  if (st != GRAVER_OK) return st;
+  {
+    Phase p3("extract: A g = 0, output");
+    st = job_finish(ctx, j, count_out);
+  }
   if (stats && (st == GRAVER_OK || st == GRAVER_E_CAPACITY)) *stats = j.stt;
   return st;
 }
@@ -615,6 +627,7 @@ extern "C" graver_status graver_extract_batch(graver_ctx* ctx, int32_t count, co
                                               const graver_batch_params* bp, graver_batch_stats* bstats) {
   if (!ctx || !probs || !params || !count_out || !bp) return set_error(GRAVER_E_INVALID, "NULL argument");
   if (count < 1 || count > 4096) return set_error(GRAVER_E_INVALID, "need 1 <= count <= 4096");
+  Phase ph("graver_extract_batch");
   for (int i = 0; i < count; ++i)
     if (params[i].collect && (!keys_out || !keys_cap)) return set_error(GRAVER_E_INVALID, "keys_out / keys_cap");
   HIP_TRY(hipSetDevice(ctx->device), "set device");

@@ -81,6 +81,7 @@ extern "C" graver_status graver_solve(graver_ctx* ctx, const graver_problem* pro
                                       graver_solve_stats* stats) {
   if (!ctx || !prob || !f || !prm || !x_best || !f_best) return set_error(GRAVER_E_INVALID, "NULL argument");
   HIP_TRY(hipSetDevice(ctx->device), "set device");
+  Phase ph("graver_solve (MAPE)");
   if (prob->m < 1 || prob->n < 1 || prob->n > 4096)
     return set_error(GRAVER_E_INVALID, "need m >= 1 and 1 <= n <= 4096");
   if (!prob->A || !prob->b || !prob->l || !prob->u)
