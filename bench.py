@@ -60,26 +60,29 @@ def descent_roofline(n, d, N, T, ms, bf16_iters=0):
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_descent_f32_qp_m20_n100_hbm_traffic.md")
 KERNEL_SOURCES = ["paper_2412_13576_amd/csrc/descent_f32.hip", "paper_2412_13576_amd/csrc/graver_internal.h",
                   "paper_2412_13576_amd/csrc/pool_device.h"]
+TRAFFIC_PROFILE_BIG = os.path.join(ROOT, "profiles", "k_descent_big_quartic_m50_n400_hbm_traffic.md")
+KERNEL_SOURCES_BIG = ["paper_2412_13576_amd/csrc/descent_big.hip", "paper_2412_13576_amd/csrc/graver_internal.h"]
 
 
-def kernel_sources_sha256() -> str:
+def kernel_sources_sha256(sources=None) -> str:
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in (sources or KERNEL_SOURCES):
         with open(os.path.join(ROOT, rel), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def _measured_traffic(N, T, precision):
+def _measured_traffic(N, T, precision, profile=None, sources=None):
     """Bytes per descent launch recorded for these sources and this launch
     shape, or None."""
+    profile = profile or TRAFFIC_PROFILE
     try:
-        with open(TRAFFIC_PROFILE) as fh:
+        with open(profile) as fh:
             kv = dict(line.split(":", 1) for line in fh if ":" in line and not line.startswith(("#", "|", "`")))
     except OSError:
         return None
     kv = {k.strip(): v.strip() for k, v in kv.items()}
-    if kv.get("source_sha256") != kernel_sources_sha256():
+    if kv.get("source_sha256") != kernel_sources_sha256(sources):
         return None
     if kv.get("launch") != f"N={N} T={T} {precision}":
         return None
@@ -107,17 +110,16 @@ def _oracle_worker(args, barrier, out):
     out.put(_oracle_extract(*args))
 
 
-def _cpu_baseline(inst, T):
-    """The oracle on the host cores, on a bounded sample of the workload (512
-    starts per process at the full T): one process, then one process per core
-    started together.  Runs before this process touches the GPU, so the worker
-    processes are plain interpreters.  start-iterations/s."""
+def _cpu_baseline(inst, T, n_sample=512):
+    """The oracle on the host cores, on a bounded sample of the workload
+    (n_sample starts per process, T iterations): one process, then one
+    process per core started together.  Runs before this process touches the
+    GPU, so the worker processes are plain interpreters.  start-iterations/s."""
     import multiprocessing as mp
 
     from oracle import lattice
     B = lattice.kernel_basis(inst.A)
     P = lattice.coordinate_projector(B)
-    n_sample = 512
     single = _oracle_extract(inst.A, B, P, inst.l, inst.u, 99, n_sample, T)
     procs = max(1, min(16, len(os.sched_getaffinity(0))))
     ctx = mp.get_context("spawn")
@@ -297,23 +299,21 @@ def bench_batch(args):
     ctx.close()
 
 
-def bench_serve(args):
-    """Serving: Poisson arrivals at 50 requests/s, n log-uniform in
-    [20, 1000], m = round(0.2 n), A iid (0 w.p. 0.8, else +-1, +-2), quadratic
-    (box [-5,5]) or separable quartic objective (box [-20,20]) 50/50, binary32
-    or bf16 descent 50/50,
-    16 n starts x 500 iterations, 8 initial-solution starts plus the
-    instance's feasible point."""
+def _serve_run(R, n_max=1000, rate=50.0, seed=5000):
+    """R Poisson arrivals at `rate`/s, n log-uniform in [20, n_max], m =
+    round(0.2 n), A iid (0 w.p. 0.8, else +-1, +-2), quadratic (box [-5,5])
+    or separable quartic objective (box [-20,20]) 50/50, binary32 or bf16
+    descent 50/50, 16 n starts x 500 iterations, 8 initial-solution starts
+    plus the instance's feasible point.  Returns the measured figures."""
     from paper_2412_13576_amd import graver as G
     from paper_2412_13576_amd import workloads as W
-    R = args.requests
-    rng = np.random.default_rng(5000)
-    ns = np.exp(rng.uniform(np.log(20), np.log(1000), size=R)).astype(int)
-    arrivals = np.cumsum(rng.exponential(1.0 / 50.0, size=R))
+    rng = np.random.default_rng(seed)
+    ns = np.exp(rng.uniform(np.log(20), np.log(n_max), size=R)).astype(int)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=R))
     reqs = []
     for k, n in enumerate(ns):
         m = max(1, int(round(0.2 * n)))
-        inst = W.sparse_quadratic_instance(5000 + k, int(n), m)
+        inst = W.sparse_quadratic_instance(seed + k, int(n), m)
         N = 16 * int(n)
         bf = rng.random() < 0.5
         ex = G.extract_params(N, 500, precision=G.GRAVER_BF16 if bf else G.GRAVER_FP32, init_mode=0, seed=k,
@@ -346,18 +346,24 @@ def bench_serve(args):
     lat = np.array([r["t_done"] - r["t_submit"] for r in ok]) * 1e3
     queue = np.array([r["t_admit"] - r["t_ready"] for r in ok]) * 1e3
     prep = np.array([r["t_ready"] - r["t_submit"] for r in ok]) * 1e3
+    gpu = np.array([r["t_done"] - r["t_admit"] for r in ok]) * 1e3
+    pct = lambda x: {"p50": float(np.percentile(x, 50)), "p99": float(np.percentile(x, 99))}
     iters = sum(N * 500 for (*_, N), r in zip(reqs, results) if r["status"] == 0)
-    _line("requests/s at Poisson 50 req/s arrivals (p50/p99 solve latency beside)", len(ok) / el, "requests/s", R, 0,
-          el * 1e3 / R, "f32|bf16",
+    return {"requests": R, "rate_per_s": rate, "n_range": [20, n_max], "wall_s": el, "completed_per_s": len(ok) / el,
+            "failed": len(results) - len(ok), "latency_ms": dict(pct(lat), max=float(lat.max())),
+            "basis_ms": pct(prep), "queue_ms": pct(queue), "gpu_ms": pct(gpu),
+            "start_iterations_per_s": iters / el, "mean_batch_size": float(np.mean([r["batch_size"] for r in ok]))}
+
+
+def bench_serve(args):
+    """Serving: the request stream of _serve_run at 50 requests/s, n up to 1000."""
+    R = args.requests
+    r = _serve_run(R)
+    _line("requests/s at Poisson 50 req/s arrivals (p50/p99 solve latency beside)", r["completed_per_s"],
+          "requests/s", R, 0, r["wall_s"] * 1e3 / R, "f32|bf16",
           {"workload": "Poisson 50/s, n log-uniform [20,1000], m = round(0.2 n), A iid density 0.2 in +-1,+-2, "
                        "quadratic (box [-5,5]) or quartic (box [-20,20]), fp32 or bf16, 16 n starts x 500 "
-                       "iterations", "requests": R},
-          latency_ms={"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                      "max": float(lat.max())},
-          basis_ms={"p50": float(np.percentile(prep, 50)), "p99": float(np.percentile(prep, 99))},
-          queue_ms={"p50": float(np.percentile(queue, 50)), "p99": float(np.percentile(queue, 99))},
-          failed=len(results) - len(ok), start_iterations_per_s=iters / el,
-          mean_batch_size=float(np.mean([r["batch_size"] for r in ok])))
+                       "iterations", "requests": R}, **{k: v for k, v in r.items() if k not in ("requests",)})
 
 
 def bench_augment(args):
@@ -411,36 +417,155 @@ def bench_augment(args):
     ctx.close()
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--starts", type=int, default=0, help="starts (default: the configuration's)")
-    ap.add_argument("--iters", type=int, default=2000)
-    ap.add_argument("--aug-starts", type=int, default=200)
-    ap.add_argument("--precision", choices=["fp32", "bf16"], default="fp32")
-    ap.add_argument("--polish", type=int, default=200, help="bf16: final iterations in binary32")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--config", choices=["qp", "precision", "batch", "serve", "augment"], default="qp",
-                    help="qp: the benchmark workload (default); the others measure the precision, "
-                         "batching and serving configurations")
-    ap.add_argument("--requests", type=int, default=300, help="serve: number of requests")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run one 1 GiB device copy (a kernel of known traffic, for counter scaling)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py runs on one GPU only: the hot path is measured on one MI355X "
-              "(multi-GPU sharding is described in DESIGN.md, not run)", file=sys.stderr)
-        sys.exit(2)
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
-    if args.copy_calibration:
-        _copy_calibration()
-    if args.config != "qp":
-        {"precision": bench_precision, "batch": bench_batch, "serve": bench_serve,
-         "augment": bench_augment}[args.config](args)
-        return
 
+def bench_quartic(args):
+    """The whole path on the largest single-GPU configuration: the quartic
+    workload (m = 50, n = 400, d = 350, 4 nonzeros per row in +-1..+-5,
+    separable degree-4 f, box [-20, 20]), 262144 box starts x 2000 binary32
+    iterations per step: Parallel Extraction with collection (about 9.5e7
+    distinct verified candidates), the minimality filter over all of them,
+    and the augmentation from 200 feasible starts.  The context's workspace is
+    released between the stages (graver_ctx_trim), since the extraction's pool
+    and the filter's buffers each need most of the device memory; that and
+    the allocations are inside the timed step.  Beside: one step with the
+    bf16 form (exact three-part bf16 forward, last 10% binary32 polish) and a
+    short serving leg."""
+    from paper_2412_13576_amd import workloads as W
+
+    inst = W.quartic_instance()
+    N, T, S0 = args.starts or 262144, args.iters, args.aug_starts
+    # the host baseline runs first, before anything here touches the GPU; the
+    # sample is bounded (64 starts x 1000 iterations per process)
+    cpu = None if args.no_cpu_baseline else _cpu_baseline(inst, min(T, 1000), n_sample=64)
+
+    import torch
+
+    from paper_2412_13576_amd import graver as G
+
+    B, P = G.kernel_basis(inst.A)              # host C++ (Lemma 3.1 + LLL), not timed
+    n, d = B.shape
+    ctx = G.Context(0)
+    prob = G.DeviceProblem.from_numpy(inst.A, inst.b, inst.l, inst.u, B, P)
+    obj = G.objective("separable_poly", coef=inst.coef)
+    starts = torch.tensor(W.feasible_walk_starts(inst.x0, B.T.copy(), inst.l, inst.u, S0, seed=7, walk_len=32),
+                          device="cuda")
+    pool_cap = max(1 << 22, 500 * N)
+
+    def step(seed, prec):
+        polish = T // 10 if prec == G.GRAVER_BF16 else 0
+        prm = G.extract_params(N, T, precision=prec, init_mode=0, seed=seed, pool_capacity=pool_cap,
+                               polish_iters=polish, any_order=True)  # the filter sorts
+        t0 = time.perf_counter()
+        keys, st = G.extract(ctx, prob, prm)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ctx.trim()
+        F = G.filter_minimal(ctx, keys)
+        K = int(keys.shape[0])
+        del keys
+        ctx.trim()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        x, f, steps, best = G.augment(ctx, prob, obj, F, starts)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        rec = dict(unique=K, filtered=int(F.shape[0]), stats=st, t_extract=t1 - t0, t_filter=t2 - t1,
+                   t_augment=t3 - t2, best_f=float(f[best].item()), mean_steps=float(steps.double().mean().item()))
+        del F
+        return rec
+
+    for w in range(args.warmup):
+        step(1000 + w, G.GRAVER_FP32)
+        print(f"[quartic] warmup step {w} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    recs = []
+    for k in range(args.steps):
+        recs.append(step(2000 + k, G.GRAVER_FP32))
+        print(f"[quartic] step {k}: {recs[-1]['t_extract']:.2f} + {recs[-1]['t_filter']:.2f} + "
+              f"{recs[-1]['t_augment']:.2f} s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms_step = el * 1000.0 / args.steps
+    desc_ms = float(np.mean([r["stats"]["ms_descent"] for r in recs]))
+    roof = descent_roofline(n, d, N, T, desc_ms)
+    mean = lambda key: float(np.mean([r[key] for r in recs]))
+    out = {
+        "metric": "start-iterations/s (whole path: extraction + filter + augmentation)",
+        "value": N * T * args.steps / el,
+        "unit": "start-iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "quartic_m50_n400: m=50, n=400 (d=350), A with 4 nonzeros per row in +-1..+-5, "
+                               "separable degree-4 f, box [-20,20] (the precision configuration's instance, binary32 "
+                               "form)", "starts": N, "iters": T, "aug_starts": S0, "precision": "fp32-mfma"},
+        "verified_directions_per_s": mean("unique") / (ms_step * 1e-3),
+        "verified_directions_per_s_extraction": mean("unique") / mean("t_extract"),
+        "descent_start_iterations_per_s": N * T / (desc_ms * 1e-3),
+        "stage_s": {"extract": mean("t_extract"), "filter": mean("t_filter"), "augment": mean("t_augment")},
+        "extract": {k: float(np.mean([r["stats"][k] for r in recs])) for k in
+                    ("emit_events", "inbox_events", "unique", "verified", "out_of_range",
+                     "ms_init", "ms_descent", "ms_verify", "ms_sort")},
+        "filtered": mean("filtered"),
+        "aug_best_f": recs[-1]["best_f"],
+        "aug_mean_steps": recs[-1]["mean_steps"],
+        "roofline": {"bound": "mfma", "kernel": "k_descent_big<2,12,fp32>", "achieved": roof["achieved"],
+                     "peak": roof["peak"], "unit": "TFLOP/s", "frac": roof["frac"],
+                     "traffic": _measured_traffic(N, T, "fp32", TRAFFIC_PROFILE_BIG, KERNEL_SOURCES_BIG),
+                     "algorithmic": "4*n*d flop per start-iteration (B z forward + B^T sign backward)",
+                     "peak_note": roof["peak_note"]},
+    }
+    if not args.no_bf16_line:
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        rb = step(3000, G.GRAVER_BF16)
+        torch.cuda.synchronize()
+        elb = time.perf_counter() - tb
+        rfb = descent_roofline(n, d, N, T, rb["stats"]["ms_descent"], bf16_iters=T - T // 10)
+        out["bf16_polish"] = {
+            "start_iterations_per_s": N * T / elb, "ms_per_step": elb * 1e3,
+            "descent_ms": rb["stats"]["ms_descent"], "unique": rb["unique"], "filtered": rb["filtered"],
+            "stage_s": {"extract": rb["t_extract"], "filter": rb["t_filter"], "augment": rb["t_augment"]},
+            "speedup_descent_over_fp32": desc_ms / rb["stats"]["ms_descent"],
+            "roofline": {"achieved": rfb["achieved"], "peak": rfb["peak"], "frac": rfb["frac"], "unit": "TFLOP/s"},
+            "form": "forward on bf16 matrix cores with z split exactly into three bf16 parts, fp32 accumulation; "
+                    f"last {T // 10} iterations binary32"}
+        print(f"[quartic] bf16 step {elb:.2f} s", file=sys.stderr, flush=True)
+    ctx.close()
+    del starts
+    torch.cuda.empty_cache()
+    if args.serve_leg > 0:
+        r = _serve_run(args.serve_leg, n_max=300)
+        out["serving_leg"] = dict(r, note="short leg of the serving configuration with n capped at 300 (host "
+                                          "kernel bases of the iid law take about 2 minutes at n = 1000)")
+        print(f"[quartic] serving leg {r['completed_per_s']:.1f} req/s, p99 {r['latency_ms']['p99']:.0f} ms",
+              file=sys.stderr, flush=True)
+    if cpu is not None:
+        cpu["cpu_model"] = _cpu_model()
+        out["cpu_baseline"] = cpu
+    print(json.dumps(out), flush=True)
+
+
+def bench_qp(args):
+    """The QP workload (m = 20, n = 100, d = 80), 65536 box starts x 2000
+    binary32 iterations: extraction, filter and augmentation per step."""
     from paper_2412_13576_amd import workloads as W
 
     inst = W.qp_instance(2000)
@@ -522,6 +647,40 @@ def main():
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
     ctx.close()
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--starts", type=int, default=0, help="starts (default: the configuration's)")
+    ap.add_argument("--iters", type=int, default=2000)
+    ap.add_argument("--aug-starts", type=int, default=200)
+    ap.add_argument("--precision", choices=["fp32", "bf16"], default="fp32")
+    ap.add_argument("--polish", type=int, default=200, help="bf16: final iterations in binary32")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--config", choices=["quartic", "qp", "precision", "batch", "serve", "augment"],
+                    default="quartic",
+                    help="quartic: the whole path on the largest single-GPU configuration (default); qp: the "
+                         "QP workload; the others measure the precision, batching and serving configurations")
+    ap.add_argument("--serve-leg", type=int, default=60,
+                    help="quartic: requests of the short serving leg reported beside (0: none)")
+    ap.add_argument("--no-bf16-line", action="store_true", help="quartic: skip the bf16 + polish step")
+    ap.add_argument("--requests", type=int, default=300, help="serve: number of requests")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one 1 GiB device copy (a kernel of known traffic, for counter scaling)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the hot path is measured on one MI355X "
+              "(multi-GPU sharding is described in DESIGN.md, not run)", file=sys.stderr)
+        sys.exit(2)
+
+    if args.copy_calibration:
+        _copy_calibration()
+    {"quartic": bench_quartic, "qp": bench_qp, "precision": bench_precision, "batch": bench_batch,
+     "serve": bench_serve, "augment": bench_augment}[args.config](args)
+
 
 
 if __name__ == "__main__":
