@@ -387,12 +387,18 @@ __global__ __launch_bounds__(kTileRows) void k_codes(const int8_t* keys, int str
 }
 
 // masks in bucket order: bmask row e = mask row bl[e] (a thread per word)
-__global__ void k_bucket_masks(const uint32_t* bl, const uint64_t* mask, uint32_t count, int W, uint64_t* bmask) {
+// (and the first word of each half again, as one 16-byte pair per member:
+// the join's fast test reads only those)
+__global__ void k_bucket_masks(const uint32_t* bl, const uint64_t* mask, uint32_t count, int W, uint64_t* bmask,
+                               uint64_t* bfirst) {
   const uint64_t total = (uint64_t)count * 2 * W;
   for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (uint64_t)gridDim.x * blockDim.x) {
     const uint64_t e = t / (2 * W);
     const int w = (int)(t - e * 2 * W);
-    bmask[e * 2 * W + w] = mask[(size_t)bl[e] * 2 * W + w];
+    const uint64_t v = mask[(size_t)bl[e] * 2 * W + w];
+    bmask[e * 2 * W + w] = v;
+    if (w == 0) bfirst[2 * e] = v;
+    if (w == W) bfirst[2 * e + 1] = v;
   }
 }
 
@@ -437,13 +443,15 @@ __global__ __launch_bounds__(kJoinThreads) void k_pairs_join(const int8_t* keys,
                                                            const uint32_t* __restrict__ lo,
                                                            const uint32_t* __restrict__ off,
                                                            const uint32_t* __restrict__ bl,
-                                                           const uint64_t* __restrict__ bmask, Coords C,
+                                                           const uint64_t* __restrict__ bmask,
+                                                           const ulonglong2* __restrict__ bfirst, Coords C,
                                                            const uint32_t* __restrict__ choff,
                                                            const uint32_t* __restrict__ owner, uint32_t ncode,
                                                            int tile_n, uint32_t* alive) {
   extern __shared__ uint64_t smem_join[];
-  uint64_t* tmask = smem_join;                                            // tile_n x 2W
-  uint32_t* tpos = reinterpret_cast<uint32_t*>(tmask + (size_t)tile_n * 2 * W);  // tile_n: position | polarity
+  ulonglong2* tfirst = reinterpret_cast<ulonglong2*>(smem_join);          // tile_n: first positive / negative words
+  uint32_t* tpos = reinterpret_cast<uint32_t*>(tfirst + tile_n);          // tile_n: position | polarity
+  uint32_t* teb = tpos + tile_n;                                          // tile_n: bucket-order index
   __shared__ uint32_t lst_b[kListCap];       // bl offset of a non-empty candidate bucket | polarity
   __shared__ uint32_t lst_pre[kListCap + 1];  // sizes, then their exclusive prefix (total at [L])
   const uint32_t lane = threadIdx.x;
@@ -544,26 +552,45 @@ __global__ __launch_bounds__(kJoinThreads) void k_pairs_join(const int8_t* keys,
           const uint32_t hb = lst_b[a];
           const uint32_t eb = (hb & ~kPolBit) + (q - lst_pre[a]);
           tpos[t] = bl[eb] | (hb & kPolBit);
-          const uint64_t* hm = bmask + (size_t)eb * 2 * W;
-          for (int w = 0; w < 2 * W; ++w) tmask[(size_t)t * 2 * W + w] = hm[w];
+          teb[t] = eb;
+          tfirst[t] = bfirst[eb];
+        }
+        // pad the tile to a multiple of 4 members that never match
+        for (uint32_t t = cnt + lane; t < ((cnt + 3u) & ~3u); t += kJoinThreads) {
+          tpos[t] = 0xFFFFFFFFu & ~kPolBit;
+          tfirst[t] = make_ulonglong2(~0ull, ~0ull);
         }
         __syncthreads();
         if (idle || dead) continue;
-        for (uint32_t t = 0; t < cnt && !dead; ++t) {
-          const uint32_t hv = tpos[t];
-          const uint32_t h = hv & ~kPolBit;
-          if (h >= my_lo) continue;
-          const bool pol = (hv & kPolBit) != 0;
-          const uint64_t* hm = tmask + (size_t)t * 2 * W;
-          uint64_t hp = hm[0], hn = hm[W];
-          bool ok = pol ? ((hp & ~gn0) | (hn & ~gp0)) == 0 : ((hp & ~gp0) | (hn & ~gn0)) == 0;
-          for (int w = 1; w < W && ok; ++w) {
-            hp = hm[w];
-            hn = hm[W + w];
-            const uint64_t gpw = gm[w], gnw = gm[W + w];
-            ok = pol ? ((hp & ~gnw) | (hn & ~gpw)) == 0 : ((hp & ~gpw) | (hn & ~gnw)) == 0;
+        // Fast test on the first 64 coordinates of the sign masks, four
+        // members at a time; the other words and the magnitudes are read only
+        // for members that pass it (for unrelated dense keys, almost none).
+        for (uint32_t t = 0; t < cnt && !dead; t += 4) {
+          bool cand[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const uint32_t hv = tpos[t + u];
+            const ulonglong2 f = tfirst[t + u];
+            const bool pol = (hv & kPolBit) != 0;
+            const uint64_t hp = f.x, hn = f.y;
+            const bool ok = pol ? ((hp & ~gn0) | (hn & ~gp0)) == 0 : ((hp & ~gp0) | (hn & ~gn0)) == 0;
+            cand[u] = ok && (hv & ~kPolBit) < my_lo;
           }
-          if (ok && magnitude_below(keys + (size_t)h * stride, g, n)) dead = true;
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            if (!cand[u] || dead) continue;
+            const uint32_t hv = tpos[t + u];
+            const uint32_t h = hv & ~kPolBit;
+            const bool pol = (hv & kPolBit) != 0;
+            const uint64_t* hm = bmask + (size_t)teb[t + u] * 2 * W;
+            bool ok = true;
+            for (int w = 1; w < W && ok; ++w) {
+              const uint64_t hp = hm[w], hn = hm[W + w];
+              const uint64_t gpw = gm[w], gnw = gm[W + w];
+              ok = pol ? ((hp & ~gnw) | (hn & ~gpw)) == 0 : ((hp & ~gpw) | (hn & ~gnw)) == 0;
+            }
+            if (ok && magnitude_below(keys + (size_t)h * stride, g, n)) dead = true;
+          }
         }
       }
     }
@@ -702,8 +729,10 @@ hipError_t launch_filter(hipStream_t s, graver_ctx* ctx, int n, const int8_t* in
   // the masks in bucket order go to the first half of the mask buffer (its
   // lexicographic-order masks are no longer read)
   uint64_t* bmsk = msk;
+  uint64_t* bfirst = (uint64_t*)ws_get(ctx, WS_F_FIRST, (size_t)U * 16 + 64, st);
+  if (!bfirst) return hipSuccess;
   hipLaunchKernelGGL(k_bucket_masks, dim3(stride_grid((uint64_t)U * 2 * W)), dim3(256), 0, s, bl, mskb, U,
-                     W, bmsk);
+                     W, bmsk, bfirst);
   HIP_RET(hipGetLastError());
   // join work items: chunks of at most kJoinThreads members of one bucket
   const size_t max_items = (size_t)(U < ncode ? U : ncode) + U / kJoinThreads + 1;
@@ -717,11 +746,11 @@ hipError_t launch_filter(hipStream_t s, graver_ctx* ctx, int n, const int8_t* in
   scan_exclusive(s, nch, choff, ncode + 1, scr2);
   hipLaunchKernelGGL(k_chunk_owner, dim3((ncode + 255) / 256), dim3(256), 0, s, nch, choff, ncode, owner);
   HIP_RET(hipGetLastError());
-  const int tile_n = W <= 4 ? 256 : (W <= 16 ? 64 : 16);
-  const size_t jshm = (size_t)tile_n * (2 * W * sizeof(uint64_t) + sizeof(uint32_t));
+  const int tile_n = 256;  // members per tile (a multiple of 4): 24 bytes each in LDS
+  const size_t jshm = (size_t)tile_n * (sizeof(ulonglong2) + 2 * sizeof(uint32_t));
   const unsigned jgrid = (unsigned)(max_items < (1u << 20) ? max_items : (1u << 20));
   hipLaunchKernelGGL(k_pairs_join, dim3(jgrid), dim3(kJoinThreads), jshm, s, canon, stride, n, W, mskb, lo, boff, bl,
-                     bmsk, C, choff, owner, ncode, tile_n, alive);
+                     bmsk, reinterpret_cast<const ulonglong2*>(bfirst), C, choff, owner, ncode, tile_n, alive);
   HIP_RET(hipGetLastError());
   // survivors back in lexicographic order: flags to lex positions, then compact uniq
   hipLaunchKernelGGL(k_scatter_flags, dim3(u256), dim3(256), 0, s, idx, alive, U, flag);
