@@ -402,12 +402,11 @@ __global__ void k_bucket_masks(const uint32_t* bl, const uint64_t* mask, uint32_
   }
 }
 
-__global__ void k_bucket_scatter(const uint32_t* code, uint32_t count, const uint32_t* off, uint32_t* cur,
-                                 uint32_t* bl) {
+// (code << bits_pos) | p: sorting these puts every bucket's members in
+// increasing position, i.e. increasing l1
+__global__ void k_code_keys(const uint32_t* code, uint32_t count, int bits_pos, uint64_t* keys) {
   uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= count) return;
-  uint32_t cd = code[p];
-  bl[off[cd] + atomicAdd(&cur[cd], 1u)] = p;
+  if (p < count) keys[p] = ((uint64_t)code[p] << bits_pos) | p;
 }
 
 // Witness search as a tiled join over the sign-pattern index.  A work item
@@ -477,6 +476,10 @@ __global__ __launch_bounds__(kJoinThreads) void k_pairs_join(const int8_t* keys,
     const bool valid = e < ge;
     const uint32_t p = valid ? bl[e] : 0u;
     const uint32_t my_lo = valid ? lo[p] : 0u;
+    // members at positions >= every key's level start cannot be witnesses;
+    // bucket lists are in increasing position, so each is cut there
+    uint32_t maxlo = my_lo;
+    for (int o = 32; o > 0; o >>= 1) maxlo = max(maxlo, (uint32_t)__shfl_xor((int)maxlo, o, 64));
     const uint64_t* gm = mask + (size_t)p * 2 * W;
     const uint64_t gp0 = valid ? gm[0] : 0ull, gn0 = valid ? gm[W] : 0ull;
     const bool idle = !valid || my_lo == 0;  // nothing of smaller l1 to test
@@ -504,6 +507,13 @@ __global__ __launch_bounds__(kJoinThreads) void k_pairs_join(const int8_t* keys,
           }
           hb = off[code];
           he = off[code + 1];
+          // first member at position >= maxlo
+          uint32_t a = hb, b = he;
+          while (a < b) {
+            const uint32_t mid = (a + b) >> 1;
+            if (bl[mid] < maxlo) a = mid + 1; else b = mid;
+          }
+          he = a;
         }
         const bool keep = he > hb;
         const uint64_t km = __ballot(keep);
@@ -711,21 +721,32 @@ hipError_t launch_filter(hipStream_t s, graver_ctx* ctx, int n, const int8_t* in
   uint32_t* code = (uint32_t*)ws_get(ctx, WS_F_CODE, ((size_t)U + n + 64) * 4, st);
   uint32_t* hist = (uint32_t*)ws_get(ctx, WS_F_HIST, ((size_t)ncode + 64) * 4, st);
   uint32_t* boff = (uint32_t*)ws_get(ctx, WS_F_OFF, ((size_t)ncode + 64) * 4, st);
-  uint32_t* cur = (uint32_t*)ws_get(ctx, WS_F_CUR, ((size_t)ncode + 64) * 4, st);
   uint32_t* bl = (uint32_t*)ws_get(ctx, WS_F_BL, (size_t)U * 4 + 64, st);
   uint32_t* scr2 = (uint32_t*)ws_get(ctx, WS_SCAN2, (((size_t)cnt > ncode ? cnt : ncode) / 512 + 256) * 4, st);
-  if (!code || !hist || !boff || !cur || !bl || !scr2) return hipSuccess;
+  if (!code || !hist || !boff || !bl || !scr2) return hipSuccess;
   const unsigned c256 = (ncode + 1 + 255) / 256;
   hipLaunchKernelGGL(k_zero32, dim3(c256), dim3(256), 0, s, hist, ncode + 1);
-  HIP_RET(hipGetLastError());
-  hipLaunchKernelGGL(k_zero32, dim3(c256), dim3(256), 0, s, cur, ncode + 1);
   HIP_RET(hipGetLastError());
   hipLaunchKernelGGL(k_codes, dim3((U + trows - 1) / trows), dim3(kTileRows), (size_t)trows * stride, s, canon, stride,
                      U, C, trows, code, hist);
   HIP_RET(hipGetLastError());
   scan_exclusive(s, hist, boff, ncode + 1, scr2);
-  hipLaunchKernelGGL(k_bucket_scatter, dim3(u256), dim3(256), 0, s, code, U, boff, cur, bl);
-  HIP_RET(hipGetLastError());
+  {
+    // bucket lists in increasing position (stable radix sort by code)
+    int bits_pos = 1;
+    while (bits_pos < 32 && ((uint64_t)1 << bits_pos) < U) ++bits_pos;
+    int bits_code = 1;
+    while (((uint64_t)1 << bits_code) < ncode) ++bits_code;
+    const uint32_t nblocks = (U + kRadixTile - 1) / kRadixTile;
+    uint64_t* rk = (uint64_t*)ws_get(ctx, WS_R_KEYS, (size_t)U * 16, st);
+    uint32_t* rh = (uint32_t*)ws_get(ctx, WS_R_HIST, (size_t)nblocks * 16 * 4 * 2 + 64, st);
+    if (!rk || !rh) return hipSuccess;
+    hipLaunchKernelGGL(k_code_keys, dim3(u256), dim3(256), 0, s, code, U, bits_pos, rk);
+    HIP_RET(hipGetLastError());
+    uint64_t* sorted = radix_sort_u64(s, rk, rk + U, U, bits_code + bits_pos, rh, rh + (size_t)nblocks * 16, scr2);
+    hipLaunchKernelGGL(k_low_bits, dim3(u256), dim3(256), 0, s, sorted, U, bits_pos, bl);
+    HIP_RET(hipGetLastError());
+  }
   // the masks in bucket order go to the first half of the mask buffer (its
   // lexicographic-order masks are no longer read)
   uint64_t* bmsk = msk;
@@ -755,7 +776,7 @@ hipError_t launch_filter(hipStream_t s, graver_ctx* ctx, int n, const int8_t* in
   // survivors back in lexicographic order: flags to lex positions, then compact uniq
   hipLaunchKernelGGL(k_scatter_flags, dim3(u256), dim3(256), 0, s, idx, alive, U, flag);
   HIP_RET(hipGetLastError());
-  scan_exclusive(s, flag, pos, U, scr);
+  scan_exclusive(s, flag, pos, U, scr2);  // (scr2: the scan slot as last sized)
   HIP_RET(hipMemcpyAsync(&hlast[0], pos + U - 1, 4, hipMemcpyDeviceToHost, s));
   HIP_RET(hipMemcpyAsync(&hlast[1], flag + U - 1, 4, hipMemcpyDeviceToHost, s));
   e = hipStreamSynchronize(s);
