@@ -617,12 +617,16 @@ hipError_t launch_filter(hipStream_t s, graver_ctx* ctx, int n, const int8_t* in
   if (cnt == 0) return hipStreamSynchronize(s);
   uint32_t p2 = 1024;
   while (p2 < cnt) p2 <<= 1;
-  int8_t* canon = (int8_t*)ws_get(ctx, WS_F_CANON, (size_t)cnt * stride, st);
+  // The two key-sized buffers take the slots of the extraction's pool and
+  // candidate log (dead once an extraction has returned its keys), so a
+  // filter that follows an extraction of the same size allocates nothing
+  // for them and the pair fits in device memory together.
+  int8_t* canon = (int8_t*)ws_get(ctx, WS_POOL_KEYS, (size_t)cnt * stride, st);
   uint32_t* idx = (uint32_t*)ws_get(ctx, WS_SORT_IDX, (size_t)p2 * 4, st);
   uint32_t* flag = (uint32_t*)ws_get(ctx, WS_FLAGS, (size_t)cnt * 4 + 64, st);
   uint32_t* pos = (uint32_t*)ws_get(ctx, WS_SCAN, (size_t)cnt * 4 + 64, st);
   uint32_t* scr = (uint32_t*)ws_get(ctx, WS_SCAN2, ((size_t)cnt / 512 + 256) * 4, st);
-  int8_t* uniq = (int8_t*)ws_get(ctx, WS_F_UNIQ, (size_t)cnt * stride, st);
+  int8_t* uniq = (int8_t*)ws_get(ctx, WS_LOG, (size_t)cnt * stride, st);
   int32_t* l1 = (int32_t*)ws_get(ctx, WS_F_L1, (size_t)cnt * 8, st);
   uint64_t* msk = (uint64_t*)ws_get(ctx, WS_F_MASK, (size_t)cnt * 4 * W * 8, st);
   uint32_t* lo = (uint32_t*)ws_get(ctx, WS_F_LO, (size_t)cnt * 4, st);
