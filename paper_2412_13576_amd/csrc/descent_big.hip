@@ -150,6 +150,18 @@ struct BigArgs {
 
 inline size_t desc_table_bytes(int count) { return ((size_t)count * sizeof(BigArgs) + 255) / 256 * 256; }
 
+// Adam's m and v stay in LDS for the whole launch (instead of streaming
+// through HBM every iteration) when they fit beside the double-buffered
+// basis chunks: 8 KB per column block of a wave for the four waves of a
+// block, with up to 4 KB left for the box widths.
+template <int CS, int DBPW, bool BF16F>
+constexpr bool mv_in_lds() {
+  const int kb = 2 * CS * DBPW + 8 * DBPW + (CS > 1 ? 8 : 0) + (BF16F && DBPW <= 12 ? 2 * DBPW : 0) + 1;
+  return kb <= 156;
+}
+template <int DBPW>
+constexpr size_t mv_lds_bytes() { return (size_t)kWaves * 2 * DBPW * 4 * 64 * sizeof(float); }
+
 __device__ __forceinline__ void zero_rows_big(const LogDev& log, uint32_t first, uint32_t rows, int lane) {
   const int dw = log.stride / 4;
   uint32_t* base = reinterpret_cast<uint32_t*>(log.rows + (size_t)first * log.stride);
@@ -177,10 +189,13 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(const BigArgs* _
   const DescentArgs& a = g.a;
   constexpr int DBT = CS * DBPW;                        // column blocks of the image
   constexpr int kChunkU4 = DBT * 64;                    // uint4 per row-block chunk
+  constexpr bool kMvLds = mv_in_lds<CS, DBPW, BF16F>();
   extern __shared__ __align__(16) unsigned char smem[];
   uint4* buf0 = reinterpret_cast<uint4*>(smem);
   uint4* buf1 = buf0 + kChunkU4;
-  int* sLim = reinterpret_cast<int*>(buf1 + kChunkU4);
+  // [chunk 0 | chunk 1 | m, v of the four waves (when in LDS) | box widths]
+  float* sMV = reinterpret_cast<float*>(buf1 + kChunkU4);
+  int* sLim = reinterpret_cast<int*>(reinterpret_cast<unsigned char*>(sMV) + (kMvLds ? mv_lds_bytes<DBPW>() : 0));
   // slice partial sums (forward, candidate) and the per-iteration exchange
   __shared__ floatx4 redY[CS > 1 ? kWaves : 1][64];
   __shared__ floatx4 redG[CS > 1 ? kWaves : 1][64];
@@ -220,6 +235,17 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(const BigArgs* _
   const float lam1 = (float)a.lambda1, lam2 = (float)a.lambda2;
   const float b1 = (float)a.beta1, b2 = (float)a.beta2, omb1 = (float)a.one_minus_b1, omb2 = (float)a.one_minus_b2;
   const float eps = (float)a.eps;
+  // this wave's m and v in LDS (same element order as the wave-native state)
+  float* sM = sMV + (size_t)wid * 2 * DBPW * 4 * 64;
+  float* sV = sM + DBPW * 4 * 64;
+  if constexpr (kMvLds) {
+    // (a rolled loop: the copy holds few registers at a time)
+#pragma unroll 1
+    for (int t = 0; t < 4 * DBPW; ++t) {
+      sM[t * 64 + lane] = M[base + t * 64];
+      sV[t * 64 + lane] = V[base + t * 64];
+    }
+  }
   const uint4* img = reinterpret_cast<const uint4*>(g.img);
   uint32_t* srow = reinterpret_cast<uint32_t*>(g.scratch + (size_t)sidx * stride);
 
@@ -490,6 +516,43 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(const BigArgs* _
     const double bc1 = a.bc[2 * k], bc2 = a.bc[2 * k + 1];
     const float step = (float)(a.lr / bc1), ib2 = (float)(1.0 / bc2);
     int ch = 0;
+    if constexpr (kMvLds) {
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int g0 = 0; g0 < DBPW; g0 += 4) {
+        // one group of 4 column blocks: load its m and v, update, store
+        float mm[4][4], vv[4][4];
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int e = (4 * (g0 + jj) + r) * 64 + lane;
+            mm[jj][r] = sM[e];
+            vv[jj][r] = sV[e];
+          }
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+          const int jb = g0 + jj;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int e = (4 * jb + r) * 64 + lane;
+            const float zj = z[jb][r];
+            float gg = G[jb][r] + lam1 * ((ceilf(zj) + floorf(zj)) - 2.f * zj);
+            if (bar && fabsf(zj) == mu) gg -= zj > 0.f ? wbar : -wbar;
+            const float mj = b1 * mm[jj][r] + omb1 * gg;
+            const float vj = b2 * vv[jj][r] + omb2 * (gg * gg);
+            const float zn = zj - (step * mj) * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(vj * ib2) + eps);
+            ch |= (rintf(zn) != rintf(zj)) | (k == 0);
+            z[jb][r] = zn;
+            sM[e] = mj;
+            sV[e] = vj;
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      changed = xor4(ch);
+      continue;
+    }
     // Opaque per-iteration copies of the base pointers: stops the compiler
     // from hoisting every element address out of the loop (each 64-bit
     // address would stay live in two VGPRs).
@@ -549,6 +612,13 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(const BigArgs* _
   for (int jb = 0; jb < DBPW; ++jb)
 #pragma unroll
     for (int r = 0; r < 4; ++r) Z[base + (4 * jb + r) * 64] = z[jb][r];
+  if constexpr (kMvLds) {
+#pragma unroll 1
+    for (int t = 0; t < 4 * DBPW; ++t) {
+      M[base + t * 64] = sM[t * 64 + lane];
+      V[base + t * 64] = sV[t * 64 + lane];
+    }
+  }
   if (lleft > 0) zero_rows_big(log, lbase + lused, (uint32_t)lleft, lane);
   for (int o = 32; o > 0; o >>= 1) {
     n_emit += __shfl_xor(n_emit, o, 64);
@@ -564,7 +634,8 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(const BigArgs* _
 
 template <int CS, int DBPW, bool BF16F>
 hipError_t launch_big_t(hipStream_t s, const void* dev_desc, int count, int64_t total_blocks, int max_nb) {
-  const size_t shmem = (size_t)2 * CS * DBPW * 64 * 16 + (size_t)16 * max_nb * sizeof(int);
+  const size_t shmem = (size_t)2 * CS * DBPW * 64 * 16 + (mv_in_lds<CS, DBPW, BF16F>() ? mv_lds_bytes<DBPW>() : 0) +
+                       (size_t)16 * max_nb * sizeof(int);
   auto kern = k_descent_big<CS, DBPW, BF16F>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
   if (e != hipSuccess) return e;
