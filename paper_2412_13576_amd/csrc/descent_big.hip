@@ -7,8 +7,10 @@
 // SIMD), i.e. 4 / CS start groups.  The basis is streamed through LDS one
 // 16-row block at a time (double buffered: the next block is loaded from
 // HBM/L2 straight into LDS while the current one is used).  z and the gradient
-// accumulators stay in registers; m and v are read and written once per
-// iteration in the wave-native layout.  Per row block ib each wave computes
+// accumulators stay in registers; Adam's m and v stay in LDS for the whole
+// launch where they fit beside the two basis chunks, and are otherwise read
+// and written once per iteration in the wave-native layout.  Per row block ib
+// each wave computes
 //   y_ib   = B_ib z      over its own columns (binary32 MFMA, or the exact
 //                        three-part bf16 split of z), summed over the slices
 //                        through LDS
