@@ -225,7 +225,9 @@ graver_status graver_extract_batch(graver_ctx* ctx, int32_t count, const graver_
 
 /* Minimality filter with deduplication (condition C3, Section 3; the
  * conformal order of Section 1).  Input: count_in int8 rows of n bytes
- * (device).  The set C = X u (-X) without 0 is formed; g in C is dropped
+ * (device), entries in [-127, 127] (the negation of every entry must be an
+ * int8; candidates of a box of widths at most 127 always are).  The set
+ * C = X u (-X) without 0 is formed; g in C is dropped
  * when some h in C, h != g, satisfies h_i g_i >= 0 and |h_i| <= |g_i| for
  * all i.  Output (device, capacity keys_cap rows): one representative per
  * pair {g, -g} (first nonzero entry positive), sorted lexicographically;

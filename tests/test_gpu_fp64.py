@@ -209,6 +209,55 @@ def test_filter_closed_form_large(G, ctx, shape):
     assert _rows(got) == want
 
 
+def _profile_set(n=100, n_atoms=24000, support=60, n_prof=16, n_sums=2_500_000, mag=60, seed=10):
+    """Closed-form key set of about 2.35 M distinct keys with entries up to
+    +-120: atoms with distinct supports of one size (an antichain) whose
+    signs follow one of n_prof sign profiles, plus sums of two atoms of the
+    same profile (each lies above both summands).  The minimal elements are
+    exactly the atoms."""
+    rng = np.random.default_rng(seed)
+    prof = rng.choice(np.array([-1, 1], np.int16), size=(n_prof, n))
+    sups = set()
+    atoms = np.zeros((n_atoms, n), np.int16)
+    which = np.arange(n_atoms) % n_prof
+    a = 0
+    while a < n_atoms:
+        s = tuple(sorted(rng.choice(n, size=support, replace=False).tolist()))
+        if s in sups:
+            continue
+        sups.add(s)
+        idx = list(s)
+        atoms[a, idx] = rng.integers(1, mag + 1, size=support) * prof[which[a], idx]
+        a += 1
+    groups = [np.flatnonzero(which == p) for p in range(n_prof)]
+    pr = rng.integers(0, n_prof, size=n_sums)
+    S = np.empty((n_sums, n), np.int8)
+    for p in range(n_prof):
+        rows = np.flatnonzero(pr == p)
+        i = rng.choice(groups[p], size=rows.size)
+        j = rng.choice(groups[p], size=rows.size)
+        j = np.where(i == j, groups[p][(np.searchsorted(groups[p], j) + 1) % groups[p].size], j)
+        S[rows] = (atoms[i] + atoms[j]).astype(np.int8)
+    X = np.concatenate([atoms.astype(np.int8), S])
+    X = X[rng.permutation(X.shape[0])]
+    neg = rng.random(X.shape[0]) < 0.5
+    X[neg] = -X[neg]
+    return X, atoms
+
+
+def test_filter_closed_form_wide_index_and_magnitudes(G, ctx):
+    """More than 2^21 distinct keys (the sign-pattern index then takes 13
+    coordinates) with entries up to +-120, so the byte-wise magnitude test
+    sees the whole int8 range the box allows."""
+    X, atoms = _profile_set()
+    _say("filter closed form profiles", X.shape, int(np.abs(X).max()))
+    assert int(np.abs(X).max()) > 100
+    want = sorted({canonical(tuple(int(v) for v in a)) for a in atoms})
+    got = G.filter_minimal(ctx, torch.tensor(X, device="cuda"))
+    assert got.shape[0] == len(want)
+    assert _rows(got) == want
+
+
 def test_filter_empty(G, ctx):
     got = G.filter_minimal(ctx, torch.zeros((0, 5), dtype=torch.int8, device="cuda"))
     assert got.shape[0] == 0
