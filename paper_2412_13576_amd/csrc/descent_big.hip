@@ -364,63 +364,58 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(const BigArgs* _
       // the other buffer was last read before the previous row block's final
       // barrier: the next row block streams into it during this one
       if (more) dma_chunk<kChunkU4>(img + (size_t)(ib + 1) * kChunkU4, nxt);
+      // this wave's operands of the row block, read from LDS once: B's
+      // columns (forward and candidate) and B^T's (backward); the B^T reads
+      // complete under the forward products
       const shortx4* FB = reinterpret_cast<const shortx4*>(cur) + jb0 * 64;
       const shortx4* BT = reinterpret_cast<const shortx4*>(cur) + (DBT + jb0) * 64;
+      shortx4 fb[DBPW], bt[DBPW];
+#pragma unroll
+      for (int jb = 0; jb < DBPW; ++jb) fb[jb] = FB[jb * 64 + lane];
+#pragma unroll
+      for (int jb = 0; jb < DBPW; ++jb) bt[jb] = BT[jb * 64 + lane];
       floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
       floatx4 gx = floatx4{0.f, 0.f, 0.f, 0.f};
       if (descend) {
-        // column blocks in groups of 4 with scheduling barriers in between
-        // (bounds the number of LDS operands loaded ahead); independent
-        // accumulators shorten the dependent MFMA chains
+        // independent accumulators shorten the dependent MFMA chains
         if constexpr (BF16F) {
           // column blocks in pairs through the 32-deep instruction, one
           // accumulator per part
           floatx4 a1 = floatx4{0.f, 0.f, 0.f, 0.f}, a2 = a1;
 #pragma unroll
-          for (int jg = 0; jg < DBPW; jg += 4) {
-#pragma unroll
-            for (int jb = jg; jb < jg + 4; jb += 2) {
-              const shortx4 A0 = FB[jb * 64 + lane], A1 = FB[(jb + 1) * 64 + lane];
-              acc = mfma_pair(A0, A1, hi[jb], hi[jb + 1], acc);
-              a1 = mfma_pair(A0, A1, mid[jb], mid[jb + 1], a1);
-              if constexpr (kLoLds)
-                a2 = mfma_pair(A0, A1, sLo[wid][jb][lane], sLo[wid][jb + 1][lane], a2);
-              else
-                a2 = mfma_pair(A0, A1, rlo[jb], rlo[jb + 1], a2);
-            }
-            __builtin_amdgcn_sched_barrier(0);
+          for (int jb = 0; jb < DBPW; jb += 2) {
+            acc = mfma_pair(fb[jb], fb[jb + 1], hi[jb], hi[jb + 1], acc);
+            a1 = mfma_pair(fb[jb], fb[jb + 1], mid[jb], mid[jb + 1], a1);
+            if constexpr (kLoLds)
+              a2 = mfma_pair(fb[jb], fb[jb + 1], sLo[wid][jb][lane], sLo[wid][jb + 1][lane], a2);
+            else
+              a2 = mfma_pair(fb[jb], fb[jb + 1], rlo[jb], rlo[jb + 1], a2);
           }
           acc += a1 + a2;
         } else {
           floatx4 a4[4] = {acc, acc, acc, acc};
 #pragma unroll
-          for (int jg = 0; jg < DBPW; jg += 4) {
+          for (int jb = 0; jb < DBPW; ++jb)
 #pragma unroll
-            for (int jb = jg; jb < jg + 4; ++jb) {
-              const shortx4 A = FB[jb * 64 + lane];
-#pragma unroll
-              for (int r = 0; r < 4; ++r)
-                a4[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(bf16_to_f(A[r]), z[jb][r], a4[r], 0, 0, 0);
-            }
-            __builtin_amdgcn_sched_barrier(0);
-          }
+            for (int r = 0; r < 4; ++r)
+              a4[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(bf16_to_f(fb[jb][r]), z[jb][r], a4[r], 0, 0, 0);
           acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
         }
       }
       if (needg) {
+        // two chains; the partial sums are integers below 2^24, so their
+        // sum is exact in any order
+        floatx4 g1 = gx;
 #pragma unroll
-        for (int jg = 0; jg < DBPW; jg += 4) {
-#pragma unroll
-          for (int jb = jg; jb < jg + 4; jb += 2)
-            gx = mfma_pair(FB[jb * 64 + lane], FB[(jb + 1) * 64 + lane], rp[jb], rp[jb + 1], gx);
-          __builtin_amdgcn_sched_barrier(0);
+        for (int jb = 0; jb < DBPW; jb += 4) {
+          gx = mfma_pair(fb[jb], fb[jb + 1], rp[jb], rp[jb + 1], gx);
+          if (jb + 2 < DBPW) g1 = mfma_pair(fb[jb + 2], fb[jb + 3], rp[jb + 2], rp[jb + 3], g1);
         }
+        gx += g1;
       }
       if constexpr (CS > 1) {
         // sum the slices' partial products in slice order (the same order in
-        // every wave of the group, so all of them hold the same y and g); the
-        // next row block goes to the other buffer, whose last reads ended
-        // before the previous row block's final barrier
+        // every wave of the group, so all of them hold the same y and g)
         if (descend) redY[wid][lane] = acc;
         if (needg) redG[wid][lane] = gx;
         __syncthreads();
@@ -435,17 +430,15 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(const BigArgs* _
           for (int c = 1; c < CS; ++c) gx += redG[gw0 + c][lane];
         }
       }
-      if (descend) {
+      {
+        // (also in the final pass, where y = 0 leaves G unchanged: the
+        // accumulators then stay in the matrix-core registers across the loop)
         shortx4 sg;
 #pragma unroll
         for (int r = 0; r < 4; ++r) sg[r] = sign_bf16(acc[r]);
 #pragma unroll
-        for (int jg = 0; jg < DBPW; jg += 4) {
-#pragma unroll
-          for (int jb = jg; jb < jg + 4; ++jb)
-            G[jb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(BT[jb * 64 + lane], sg, G[jb], 0, 0, 0);
-          __builtin_amdgcn_sched_barrier(0);
-        }
+        for (int jb = 0; jb < DBPW; ++jb)
+          G[jb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bt[jb], sg, G[jb], 0, 0, 0);
       }
       if (needg) {
         uint32_t wd = 0;
