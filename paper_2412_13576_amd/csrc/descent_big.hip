@@ -41,6 +41,7 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef short shortx4 __attribute__((ext_vector_type(4)));
 typedef short shortx8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
@@ -139,6 +140,15 @@ __device__ __forceinline__ void dma_chunk(const uint4* src, uint4* dst) {
 
 __device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }  // vmcnt(0)
 
+// Global-memory view of a pointer read from the descriptor table.  Such
+// pointers are generic, and accesses through them compile to flat
+// instructions, which also count against the LDS wait counter: every wait
+// for an LDS operand would then wait for the stores in flight as well.
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
 struct BigArgs {
   DescentArgs a;
   int NB;
@@ -166,7 +176,7 @@ constexpr size_t mv_lds_bytes() { return (size_t)kWaves * 2 * DBPW * 4 * 64 * si
 
 __device__ __forceinline__ void zero_rows_big(const LogDev& log, uint32_t first, uint32_t rows, int lane) {
   const int dw = log.stride / 4;
-  uint32_t* base = reinterpret_cast<uint32_t*>(log.rows + (size_t)first * log.stride);
+  auto base = gmem(reinterpret_cast<uint32_t*>(log.rows + (size_t)first * log.stride));
   for (uint32_t t = lane; t < rows * (uint32_t)dw; t += 64) base[t] = 0u;
 }
 
@@ -225,9 +235,9 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(const BigArgs* _
   float z[DBPW][4];
   // per-wave base pointers (uniform) with 32-bit lane offsets
   const size_t wbase = (size_t)w * 4 * DBPW * 64;
-  float* Z = g.z + wbase;
-  float* M = g.z + g.per + wbase;
-  float* V = g.z + 2 * g.per + wbase;
+  auto Z = gmem(g.z + wbase);
+  auto M = gmem(g.z + g.per + wbase);
+  auto V = gmem(g.z + 2 * g.per + wbase);
   const int base = lane;
 #pragma unroll
   for (int jb = 0; jb < DBPW; ++jb)
@@ -249,7 +259,8 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(const BigArgs* _
     }
   }
   const uint4* img = reinterpret_cast<const uint4*>(g.img);
-  uint32_t* srow = reinterpret_cast<uint32_t*>(g.scratch + (size_t)sidx * stride);
+  auto srow = gmem(reinterpret_cast<uint32_t*>(g.scratch + (size_t)sidx * stride));
+  const int lim_uniform = a.lim_uniform;
 
   int changed = 0;       // the current iterate's rounding differs from the previous one
   unsigned long long n_emit = 0, n_inbox = 0, n_range = 0;
@@ -258,6 +269,8 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(const BigArgs* _
   bool log_full = false;
   const LogDev& log = a.log;
 
+  int par = 0;  // buffer of row block 0 in the current pass
+  dma_chunk<kChunkU4>(img, buf0);
   for (int k = 0; k <= a.T; ++k) {
     const bool descend = k < a.T;
     // infinity norm and its ties, change and exact-range flags of the
@@ -285,9 +298,8 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(const BigArgs* _
 #pragma unroll
       for (int r = 0; r < 4; ++r) rmax = fmaxf(rmax, fabsf(rintf(z[jb][r])));
     int inrange = xmax4(rmax) <= 256.f;
-    // stage row block 0 (every read of the buffers in the previous
-    // iteration ended before its last barrier); the barrier below publishes it
-    dma_chunk<kChunkU4>(img, buf0);
+    // row block 0 was staged during the previous pass's last row block (or
+    // before the loop); the barrier below publishes it
     wait_vmem();
     if constexpr (CS > 1) {
       if (q == 0) {
@@ -358,12 +370,13 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(const BigArgs* _
     int inbox = 1, nonzero = 0;
 
     for (int ib = 0; ib < NB; ++ib) {
-      uint4* cur = (ib & 1) ? buf1 : buf0;
-      uint4* nxt = (ib & 1) ? buf0 : buf1;
-      const bool more = ib + 1 < NB;
+      const int pb = (par + ib) & 1;
+      uint4* cur = pb ? buf1 : buf0;
+      uint4* nxt = pb ? buf0 : buf1;
       // the other buffer was last read before the previous row block's final
-      // barrier: the next row block streams into it during this one
-      if (more) dma_chunk<kChunkU4>(img + (size_t)(ib + 1) * kChunkU4, nxt);
+      // barrier: the next row block streams into it during this one, and
+      // during the last one row block 0 of the next pass does
+      if (ib + 1 < NB || descend) dma_chunk<kChunkU4>(img + (size_t)(ib + 1 < NB ? ib + 1 : 0) * kChunkU4, nxt);
       // this wave's operands of the row block, read from LDS once: B's
       // columns (forward and candidate) and B^T's (backward); the B^T reads
       // complete under the forward products
@@ -440,23 +453,26 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(const BigArgs* _
         for (int jb = 0; jb < DBPW; ++jb)
           G[jb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bt[jb], sg, G[jb], 0, 0, 0);
       }
+      uint32_t wd = 0;
       if (needg) {
-        uint32_t wd = 0;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int gv = (int)gx[r];
-          const int lim = a.lim_uniform >= 0 ? a.lim_uniform : sLim[16 * ib + 4 * q + r];
+          const int lim = lim_uniform >= 0 ? lim_uniform : sLim[16 * ib + 4 * q + r];
           inbox &= (gv <= lim) & (gv >= -lim);
           nonzero |= gv != 0;
           wd |= ((uint32_t)(uint8_t)(int8_t)gv) << (8 * r);
         }
-        if (svalid && lead) srow[4 * ib + q] = wd;
       }
       // publishes the next row block, and (CS > 1) ends the reads of the
       // partial sums before they are rewritten
       wait_vmem();
       __syncthreads();
+      // (stored after the wait: the next row block's wait for its loads then
+      // finds the store long completed)
+      if (needg && svalid && lead) srow[4 * ib + q] = wd;
     }
+    par = (par + NB) & 1;
 
     __builtin_amdgcn_sched_barrier(0);
     if (needg) {
@@ -491,8 +507,23 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(const BigArgs* _
         } else {
           const uint32_t rank = (uint32_t)__popcll(pm & ((1ull << sl) - 1ull));
           if (put) {
-            uint32_t* row = reinterpret_cast<uint32_t*>(log.rows + (size_t)(lbase + lused + rank) * stride);
-            for (int ib = 0; ib < NB; ++ib) row[4 * ib + q] = srow[4 * ib + q];
+            // the four lanes of the start copy the staged row in 16-byte
+            // pieces, four loads issued before their stores (one round trip
+            // per 256 bytes of row); the staging stores of every lane of the
+            // wave have completed first
+            wait_vmem();
+            auto row4 = gmem(reinterpret_cast<u32x4*>(log.rows + (size_t)(lbase + lused + rank) * stride));
+            auto src4 = gmem(reinterpret_cast<u32x4*>(g.scratch + (size_t)sidx * stride));
+            const int nc = stride / 16;
+            for (int c0 = 0; c0 < nc; c0 += 16) {
+              u32x4 t[4];
+#pragma unroll
+              for (int u = 0; u < 4; ++u)
+                if (c0 + 4 * u + q < nc) t[u] = src4[c0 + 4 * u + q];
+#pragma unroll
+              for (int u = 0; u < 4; ++u)
+                if (c0 + 4 * u + q < nc) row4[c0 + 4 * u + q] = t[u];
+            }
           }
           lused += (uint32_t)npu;
           lleft -= npu;
@@ -551,8 +582,8 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(const BigArgs* _
     // Opaque per-iteration copies of the base pointers: stops the compiler
     // from hoisting every element address out of the loop (each 64-bit
     // address would stay live in two VGPRs).
-    float* Mi = M;
-    float* Vi = V;
+    auto Mi = M;
+    auto Vi = V;
     asm volatile("" : "+v"(Mi), "+v"(Vi));
     // m and v stream through registers in groups of 4 column blocks; the
     // next group's loads are issued before the current group is computed
