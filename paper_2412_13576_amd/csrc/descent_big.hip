@@ -53,7 +53,7 @@ inline int blk16(int x) { return (x + 15) / 16; }
 // Shapes with an instantiated kernel, in order of preference: the smallest
 // split whose waves hold at most 12 column blocks (wider waves exceed the
 // register file); 16 blocks per wave only beyond d = 768.
-constexpr BigShape kShapes[] = {{1, 8}, {1, 12}, {2, 8}, {2, 12}, {4, 8}, {4, 12}, {4, 16}};
+constexpr BigShape kShapes[] = {{1, 8}, {1, 12}, {2, 8}, {4, 6}, {2, 12}, {4, 8}, {4, 12}, {4, 16}};
 
 inline int64_t big_waves(int64_t N) {
   int64_t w = (N + 15) / 16;
@@ -166,8 +166,14 @@ inline size_t desc_table_bytes(int count) { return ((size_t)count * sizeof(BigAr
 // through HBM every iteration) when they fit beside the double-buffered
 // basis chunks: 8 KB per column block of a wave for the four waves of a
 // block, with up to 4 KB left for the box widths.
+// Shapes that run two waves per SIMD (two blocks per CU): registers within
+// 256 per lane and LDS within half the CU's, so Adam's m and v stay in HBM.
+template <int CS, int DBPW>
+constexpr int waves_per_simd() { return CS == 4 && DBPW == 6 ? 2 : 1; }
+
 template <int CS, int DBPW, bool BF16F>
 constexpr bool mv_in_lds() {
+  if (waves_per_simd<CS, DBPW>() > 1 || DBPW % 4 != 0) return false;
   const int kb = 2 * CS * DBPW + 8 * DBPW + (CS > 1 ? 8 : 0) + (BF16F && DBPW <= 12 ? 2 * DBPW : 0) + 1;
   return kb <= 156;
 }
@@ -183,7 +189,7 @@ __device__ __forceinline__ void zero_rows_big(const LogDev& log, uint32_t first,
 // The grid covers the start groups of every instance of the launch: block
 // b belongs to the instance i with cum[i] <= b < cum[i + 1].
 template <int CS, int DBPW, bool BF16F>
-__global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(const BigArgs* __restrict__ descs,
+__global__ __launch_bounds__(64 * kWaves, (waves_per_simd<CS, DBPW>())) void k_descent_big(const BigArgs* __restrict__ descs,
                                                                 const int64_t* __restrict__ cum, int count) {
   int inst = 0;
   {
@@ -213,6 +219,7 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(const BigArgs* _
   __shared__ floatx4 redG[CS > 1 ? kWaves : 1][64];
   __shared__ float xmu[kWaves][16], xcnt[kWaves][16];
   __shared__ int xflag[kWaves][16];
+  __shared__ int xwave[kWaves];
   // low bf16 parts of z, per lane, in LDS while they fit next to the
   // double-buffered basis chunks (widest shape: in registers)
   constexpr bool kLoLds = BF16F && DBPW <= 12;
@@ -269,8 +276,10 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(const BigArgs* _
   bool log_full = false;
   const LogDev& log = a.log;
 
+  const bool collect = a.collect != 0;
   int par = 0;  // buffer of row block 0 in the current pass
   dma_chunk<kChunkU4>(img, buf0);
+  wait_vmem();
   for (int k = 0; k <= a.T; ++k) {
     const bool descend = k < a.T;
     // infinity norm and its ties, change and exact-range flags of the
@@ -298,16 +307,23 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(const BigArgs* _
 #pragma unroll
       for (int r = 0; r < 4; ++r) rmax = fmaxf(rmax, fabsf(rintf(z[jb][r])));
     int inrange = xmax4(rmax) <= 256.f;
-    // row block 0 was staged during the previous pass's last row block (or
-    // before the loop); the barrier below publishes it
-    wait_vmem();
+    // One barrier per pass exchanges the slices' parts of the norm and the
+    // flags, and every wave's "some start of mine changed" flag, so that
+    // whether the candidates are formed is block-uniform (the row-block loop
+    // below has block barriers, and the final pass exits the loop when no
+    // wave of the block needs it).  It also publishes row block 0, staged
+    // during the previous pass's last row block (or before the loop).
     if constexpr (CS > 1) {
       if (q == 0) {
         xmu[wid][sl] = mu;
         xcnt[wid][sl] = cnt;
         xflag[wid][sl] = (changed ? 1 : 0) | (inrange ? 2 : 0);
       }
-      __syncthreads();
+    }
+    const int wchg = __ballot(changed && svalid) != 0 ? 1 : 0;
+    if (lane == 0) xwave[wid] = wchg;
+    __syncthreads();
+    if constexpr (CS > 1) {
       float gm = xmu[gw0][sl];
 #pragma unroll
       for (int c = 1; c < CS; ++c) gm = fmaxf(gm, xmu[gw0 + c][sl]);
@@ -325,10 +341,10 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(const BigArgs* _
       changed = f_or;
       inrange = f_and ? 1 : 0;
     }
-    // block-uniform (the row-block loop below has block barriers, and the
-    // final pass exits the loop when no wave of the block needs it).  The
-    // barrier is taken on every iteration: it also publishes row block 0.
-    const bool needg = __syncthreads_or((a.collect && k > 0 && changed && svalid) ? 1 : 0) != 0;
+    int anyw = 0;
+#pragma unroll
+    for (int w2 = 0; w2 < kWaves; ++w2) anyw |= xwave[w2];
+    const bool needg = collect && k > 0 && anyw != 0;
     if (!descend && !needg) break;
     // rounded coordinates of the current iterate as exact bf16 operands
     shortx4 rp[DBPW];
@@ -585,14 +601,15 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(const BigArgs* _
     auto Mi = M;
     auto Vi = V;
     asm volatile("" : "+v"(Mi), "+v"(Vi));
-    // m and v stream through registers in groups of 4 column blocks; the
+    // m and v stream through registers in groups of GW column blocks; the
     // next group's loads are issued before the current group is computed
     // (two register stages), and scheduling barriers keep the compiler from
     // hoisting every load of the iteration at once.
-    constexpr int NG = DBPW / 4;
-    float mv[2][4][4][2];
+    constexpr int GW = DBPW % 4 == 0 ? 4 : 2;
+    constexpr int NG = DBPW / GW;
+    float mv[2][GW][4][2];
 #pragma unroll
-    for (int jb = 0; jb < 4; ++jb)
+    for (int jb = 0; jb < GW; ++jb)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int e = base + (4 * jb + r) * 64;
@@ -604,17 +621,17 @@ __global__ __launch_bounds__(64 * kWaves, 1) void k_descent_big(const BigArgs* _
       const int cur = gi & 1, nx = cur ^ 1;
       if (gi + 1 < NG) {
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj)
+        for (int jj = 0; jj < GW; ++jj)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int e = base + (4 * (4 * (gi + 1) + jj) + r) * 64;
+            const int e = base + (4 * (GW * (gi + 1) + jj) + r) * 64;
             mv[nx][jj][r][0] = Mi[e];
             mv[nx][jj][r][1] = Vi[e];
           }
       }
 #pragma unroll
-      for (int jj = 0; jj < 4; ++jj) {
-        const int jb = 4 * gi + jj;
+      for (int jj = 0; jj < GW; ++jj) {
+        const int jb = GW * gi + jj;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const float zj = z[jb][r];
@@ -680,6 +697,7 @@ hipError_t launch_big_shape(hipStream_t s, BigShape sh, const void* dev_desc, in
     case 112: return launch_big_t<1, 12, BF16F>(s, dev_desc, count, total_blocks, max_nb);
     case 208: return launch_big_t<2, 8, BF16F>(s, dev_desc, count, total_blocks, max_nb);
     case 212: return launch_big_t<2, 12, BF16F>(s, dev_desc, count, total_blocks, max_nb);
+    case 406: return launch_big_t<4, 6, BF16F>(s, dev_desc, count, total_blocks, max_nb);
     case 408: return launch_big_t<4, 8, BF16F>(s, dev_desc, count, total_blocks, max_nb);
     case 412: return launch_big_t<4, 12, BF16F>(s, dev_desc, count, total_blocks, max_nb);
     case 416: return launch_big_t<4, 16, BF16F>(s, dev_desc, count, total_blocks, max_nb);
