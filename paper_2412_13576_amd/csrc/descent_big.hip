@@ -52,8 +52,10 @@ inline int blk16(int x) { return (x + 15) / 16; }
 
 // Shapes with an instantiated kernel, in order of preference: the smallest
 // split whose waves hold at most 12 column blocks (wider waves exceed the
-// register file); 16 blocks per wave only beyond d = 768.
-constexpr BigShape kShapes[] = {{1, 8}, {1, 12}, {2, 8}, {4, 6}, {2, 12}, {4, 8}, {4, 12}, {4, 16}};
+// register file); 16 blocks per wave only beyond d = 768.  The 6-block
+// shapes run two waves per SIMD: (4, 6) is preferred up to d = 384 (0.81x
+// the time of (2, 12) at d = 350); (2, 6) is an autotuner candidate.
+constexpr BigShape kShapes[] = {{1, 8}, {1, 12}, {2, 6}, {2, 8}, {4, 6}, {2, 12}, {4, 8}, {4, 12}, {4, 16}};
 
 inline int64_t big_waves(int64_t N) {
   int64_t w = (N + 15) / 16;
@@ -168,8 +170,9 @@ inline size_t desc_table_bytes(int count) { return ((size_t)count * sizeof(BigAr
 // block, with up to 4 KB left for the box widths.
 // Shapes that run two waves per SIMD (two blocks per CU): registers within
 // 256 per lane and LDS within half the CU's, so Adam's m and v stay in HBM.
+// (8 column blocks per wave need more than 256 registers.)
 template <int CS, int DBPW>
-constexpr int waves_per_simd() { return CS == 4 && DBPW == 6 ? 2 : 1; }
+constexpr int waves_per_simd() { return DBPW == 6 ? 2 : 1; }
 
 template <int CS, int DBPW, bool BF16F>
 constexpr bool mv_in_lds() {
@@ -698,6 +701,7 @@ hipError_t launch_big_shape(hipStream_t s, BigShape sh, const void* dev_desc, in
     case 208: return launch_big_t<2, 8, BF16F>(s, dev_desc, count, total_blocks, max_nb);
     case 212: return launch_big_t<2, 12, BF16F>(s, dev_desc, count, total_blocks, max_nb);
     case 406: return launch_big_t<4, 6, BF16F>(s, dev_desc, count, total_blocks, max_nb);
+    case 206: return launch_big_t<2, 6, BF16F>(s, dev_desc, count, total_blocks, max_nb);
     case 408: return launch_big_t<4, 8, BF16F>(s, dev_desc, count, total_blocks, max_nb);
     case 412: return launch_big_t<4, 12, BF16F>(s, dev_desc, count, total_blocks, max_nb);
     case 416: return launch_big_t<4, 16, BF16F>(s, dev_desc, count, total_blocks, max_nb);
