@@ -34,6 +34,11 @@ PEAK_BF16_MFMA = 2500.0  # TFLOP/s, MI355X dense bf16 matrix
 PEAK_HBM = 8000.0       # GB/s
 
 
+def _big_kernel_name(stats, form):
+    """The large-basis descent kernel an extraction ran, from its tile."""
+    return f"k_descent_big<{stats.get('tile_slices', 0)},{stats.get('tile_blocks', 0)},{form}>"
+
+
 def descent_roofline(n, d, N, T, ms, bf16_iters=0):
     """Roofline of one descent launch.  Algorithmic work: 4 n d flop per
     start-iteration, 2 n d for the forward B z and 2 n d for the backward
@@ -207,7 +212,7 @@ def bench_precision(args):
         _, st = G.extract(ctx, prob, prm)
         torch.cuda.synchronize()
         el = time.perf_counter() - t
-        res[prec] = {"descent_ms": st["ms_descent"], "wall_ms": el * 1e3,
+        res[prec] = {"descent_ms": st["ms_descent"], "wall_ms": el * 1e3, "kernel": _big_kernel_name(st, prec),
                      "start_iterations_per_s": N * T / el,
                      "tflops": 4.0 * inst.n * B.shape[1] * N * T / (st["ms_descent"] * 1e-3) / 1e12}
         print(f"[precision] {prec} descent {st['ms_descent']:.1f} ms", file=sys.stderr, flush=True)
@@ -232,7 +237,7 @@ def bench_precision(args):
           {"workload": "quartic_m50_n400: m=50, n=400 (d=350), 4 nonzeros per row in +-1..+-5, separable "
                        "quartic f, box [-20,20]", "starts": N, "iters": T, "recall_starts": Nr},
           precision=res, speedup_bf16_over_fp32=res["fp32"]["wall_ms"] / res["bf16"]["wall_ms"],
-          roofline={"bound": "mfma", "kernel": "k_descent_big<2,12>", "achieved": res["fp32"]["tflops"],
+          roofline={"bound": "mfma", "kernel": res["fp32"]["kernel"], "achieved": res["fp32"]["tflops"],
                     "peak": PEAK_FP32_MFMA, "unit": "TFLOP/s", "frac": res["fp32"]["tflops"] / PEAK_FP32_MFMA,
                     "traffic": None, "note": "binary32 launch; the bf16 launch is reported in precision.bf16"})
     ctx.close()
@@ -524,7 +529,7 @@ def bench_quartic(args):
         "filtered": mean("filtered"),
         "aug_best_f": recs[-1]["best_f"],
         "aug_mean_steps": recs[-1]["mean_steps"],
-        "roofline": {"bound": "mfma", "kernel": "k_descent_big<2,12,fp32>", "achieved": roof["achieved"],
+        "roofline": {"bound": "mfma", "kernel": _big_kernel_name(recs[-1]["stats"], "fp32"), "achieved": roof["achieved"],
                      "peak": roof["peak"], "unit": "TFLOP/s", "frac": roof["frac"],
                      "traffic": _measured_traffic(N, T, "fp32", TRAFFIC_PROFILE_BIG, KERNEL_SOURCES_BIG),
                      "algorithmic": "4*n*d flop per start-iteration (B z forward + B^T sign backward)",

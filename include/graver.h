@@ -114,6 +114,8 @@ typedef struct {
   int64_t verified;         /* distinct candidates with A g = 0              */
   int64_t out_of_range;     /* iterates with a coordinate beyond the exact range */
   double ms_init, ms_descent, ms_verify, ms_sort; /* device time per phase  */
+  int32_t tile_slices;      /* large-basis kernel: waves per start group     */
+  int32_t tile_blocks;      /* and 16-column blocks per wave (0 otherwise)    */
 } graver_extract_stats;
 
 typedef struct {

@@ -380,6 +380,10 @@ graver_status job_setup(graver_ctx* ctx, Job& j, bool force_big, bool autotune) 
     HIP_TRY(launch_big_pack(s, n, d, j.sh, prob->B, j.img), "pack basis");
   }
   j.DBlay = small ? (d + 15) / 16 : j.sh.cs * j.sh.dbpw;
+  if (!small) {
+    j.stt.tile_slices = j.sh.cs;
+    j.stt.tile_blocks = j.sh.dbpw;
+  }
   const size_t sfloats = small ? f32_state_floats(n, d, N) : big_state_floats(j.sh, N);
   j.fstate = (float*)W(ctx, j, WS_MF_STATE, sfloats * sizeof(float), &st);
   if (!j.fstate) return st;

@@ -66,7 +66,8 @@ class ExtractStats(C.Structure):
     _fields_ = [("start_iterations", C.c_int64), ("emit_events", C.c_int64),
                 ("inbox_events", C.c_int64), ("unique", C.c_int64), ("verified", C.c_int64),
                 ("out_of_range", C.c_int64), ("ms_init", C.c_double), ("ms_descent", C.c_double),
-                ("ms_verify", C.c_double), ("ms_sort", C.c_double)]
+                ("ms_verify", C.c_double), ("ms_sort", C.c_double),
+                ("tile_slices", C.c_int32), ("tile_blocks", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
