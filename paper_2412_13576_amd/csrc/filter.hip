@@ -436,6 +436,16 @@ constexpr int kListCap = 256;
 constexpr int kListPerLane = kListCap / kJoinThreads;
 constexpr uint32_t kPolBit = 0x80000000u;
 
+// bit c of bits: bucket c is non-empty (the join tests it before reading
+// the bucket's offsets)
+__global__ void k_bucket_bits(const uint32_t* hist, uint32_t ncode, uint32_t* bits) {
+  const uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w * 32u >= ncode) return;
+  uint32_t v = 0;
+  for (uint32_t b = 0; b < 32u && w * 32u + b < ncode; ++b) v |= (hist[w * 32u + b] != 0 ? 1u : 0u) << b;
+  bits[w] = v;
+}
+
 // Work items of the join: bucket G is cut into ceil(size / kJoinThreads)
 // chunks of consecutive members; owner[w] = bucket of chunk w, and the
 // chunks of G start at item choff[G].
@@ -459,13 +469,17 @@ __global__ __launch_bounds__(kJoinThreads) void k_pairs_join(const int8_t* keys,
                                                            const ulonglong2* __restrict__ bfirst, Coords C,
                                                            const uint32_t* __restrict__ choff,
                                                            const uint32_t* __restrict__ owner, uint32_t ncode,
-                                                           int tile_n, uint32_t* alive) {
+                                                           const uint32_t* __restrict__ bits, int tile_n,
+                                                           uint32_t* alive) {
   extern __shared__ uint64_t smem_join[];
   ulonglong2* tfirst = reinterpret_cast<ulonglong2*>(smem_join);          // tile_n: first positive / negative words
   uint32_t* tpos = reinterpret_cast<uint32_t*>(tfirst + tile_n);          // tile_n: position
   uint32_t* teb = tpos + tile_n;                                          // tile_n: bucket-order index | polarity
   __shared__ uint32_t lst_b[kListCap];       // bl offset of a non-empty candidate bucket | polarity
   __shared__ uint32_t lst_pre[kListCap + 1];  // sizes, then their exclusive prefix (total at [L])
+  // the item's candidate codes: code(j) = tcode[pol][0][j & 255] +
+  // tcode[pol][1][j >> 8] for subset j of the item's nonzero digits
+  __shared__ uint32_t tcode[2][2][256];
   const uint32_t lane = threadIdx.x;
   const uint32_t nwork = choff[ncode];
   for (uint32_t wk = blockIdx.x; wk < nwork; wk += gridDim.x) {
@@ -485,6 +499,22 @@ __global__ __launch_bounds__(kJoinThreads) void k_pairs_join(const int8_t* keys,
 #pragma unroll
     for (int i = 0; i < kMaxC; ++i) z += dg[i] != 0;
     const uint32_t nsub = 1u << z;
+    __syncthreads();  // the previous item's code tables are no longer read
+    for (uint32_t e = lane; e < 4u * 256u; e += kJoinThreads) {
+      const uint32_t pol = e >> 9, half = (e >> 8) & 1u, sub = e & 255u;
+      uint32_t code = 0;
+      int bit = 0;
+#pragma unroll
+      for (int i = 0; i < kMaxC; ++i) {
+        if (dg[i]) {
+          const int hb8 = bit - 8 * (int)half;
+          if (hb8 >= 0 && hb8 < 8 && ((sub >> hb8) & 1u)) code += (uint32_t)((pol ? 3 - dg[i] : dg[i]) * C.pow3[i]);
+          ++bit;
+        }
+      }
+      tcode[pol][half][sub] = code;
+    }
+    __syncthreads();
     const uint32_t e = gb + lane;
     const bool valid = e < ge;
     const uint32_t p = valid ? bl[e] : 0u;
@@ -509,24 +539,18 @@ __global__ __launch_bounds__(kJoinThreads) void k_pairs_join(const int8_t* keys,
         if (j < 2 * nsub) {
           pol = j >= nsub ? 1u : 0u;
           const uint32_t sidx = j - pol * nsub;
-          uint32_t code = 0;
-          int bit = 0;
-#pragma unroll
-          for (int i = 0; i < kMaxC; ++i) {
-            if (dg[i]) {
-              if ((sidx >> bit) & 1u) code += (uint32_t)((pol ? 3 - dg[i] : dg[i]) * C.pow3[i]);
-              ++bit;
+          const uint32_t code = tcode[pol][0][sidx & 255u] + tcode[pol][1][sidx >> 8];
+          if ((bits[code >> 5] >> (code & 31u)) & 1u) {
+            hb = off[code];
+            he = off[code + 1];
+            // first member at position >= maxlo
+            uint32_t a = hb, b = he;
+            while (a < b) {
+              const uint32_t mid = (a + b) >> 1;
+              if (bl[mid] < maxlo) a = mid + 1; else b = mid;
             }
+            he = a;
           }
-          hb = off[code];
-          he = off[code + 1];
-          // first member at position >= maxlo
-          uint32_t a = hb, b = he;
-          while (a < b) {
-            const uint32_t mid = (a + b) >> 1;
-            if (bl[mid] < maxlo) a = mid + 1; else b = mid;
-          }
-          he = a;
         }
         const bool keep = he > hb;
         const uint64_t km = __ballot(keep);
@@ -787,11 +811,15 @@ hipError_t launch_filter(hipStream_t s, graver_ctx* ctx, int n, const int8_t* in
   scan_exclusive(s, nch, choff, ncode + 1, scr2);
   hipLaunchKernelGGL(k_chunk_owner, dim3((ncode + 255) / 256), dim3(256), 0, s, nch, choff, ncode, owner);
   HIP_RET(hipGetLastError());
+  uint32_t* bits = (uint32_t*)ws_get(ctx, WS_F_BITS, ((size_t)ncode / 32 + 64) * 4, st);
+  if (!bits) return hipSuccess;
+  hipLaunchKernelGGL(k_bucket_bits, dim3((ncode / 32 + 1 + 255) / 256), dim3(256), 0, s, hist, ncode, bits);
+  HIP_RET(hipGetLastError());
   const int tile_n = 256;  // members per tile (a multiple of 4): 24 bytes each in LDS
   const size_t jshm = (size_t)tile_n * (sizeof(ulonglong2) + 2 * sizeof(uint32_t));
   const unsigned jgrid = (unsigned)(max_items < (1u << 20) ? max_items : (1u << 20));
   hipLaunchKernelGGL(k_pairs_join, dim3(jgrid), dim3(kJoinThreads), jshm, s, canon, stride, n, W, mskb, lo, boff, bl,
-                     bmsk, reinterpret_cast<const ulonglong2*>(bfirst), C, choff, owner, ncode, tile_n, alive);
+                     bmsk, reinterpret_cast<const ulonglong2*>(bfirst), C, choff, owner, ncode, bits, tile_n, alive);
   HIP_RET(hipGetLastError());
   // survivors back in lexicographic order: flags to lex positions, then compact uniq
   hipLaunchKernelGGL(k_scatter_flags, dim3(u256), dim3(256), 0, s, idx, alive, U, flag);

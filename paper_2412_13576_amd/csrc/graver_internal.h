@@ -102,7 +102,7 @@ enum Slot : int {
   WS_F_CANON, WS_F_UNIQ, WS_F_L1, WS_F_MASK, WS_F_LO, WS_F_ALIVE, WS_F_CHUNK,
   WS_A_R, WS_A_PART, WS_A_DONE, WS_A_QG, WS_A_TAB,
   WS_MF_B, WS_MF_BT, WS_MF_STATE, WS_MISC,
-  WS_F_CODE, WS_F_HIST, WS_F_OFF, WS_F_CUR, WS_F_BL, WS_LOG, WS_LOG_COUNT, WS_MF_BAK, WS_MISC2,
+  WS_F_CODE, WS_F_HIST, WS_F_OFF, WS_F_BITS, WS_F_BL, WS_LOG, WS_LOG_COUNT, WS_MF_BAK, WS_MISC2,
   WS_I_X, WS_I_M, WS_I_V, WS_I_R, WS_I_G,
   WS_S_KEYS, WS_S_F, WS_S_SOL, WS_S_FEAS, WS_S_IDX, WS_S_STARTS, WS_S_X, WS_S_FV, WS_S_STEPS, WS_S_B, WS_S_P,
   WS_V_CSR, WS_BIG_DESC, WS_R_KEYS, WS_R_HIST, WS_STEPF, WS_F_FIRST,
