@@ -722,16 +722,17 @@ hipError_t launch_filter(hipStream_t s, graver_ctx* ctx, int n, const int8_t* in
   // sign-pattern index on the k most frequently nonzero coordinates.  A work
   // item enumerates up to 2 * 2^k codes, while the members it tests shrink
   // geometrically with k (for dense keys by about half per coordinate), so
-  // k grows with log2 U: about log2(U) / 2 + 2, at most kMaxC (on 9.6e7 dense
-  // keys of n = 400, k = 12 / 13 / 14 / 15 / 16 measured 5.27 / 3.46 / 2.62
-  // / 2.34 / 2.44 s for the whole filter).
+  // k grows with log2 U: about log2(U) / 2 + 3, at most kMaxC (on 9.6e7 dense
+  // keys of n = 400, k = 13 / 14 / 15 / 16 measured 2.72 / 1.79 / 1.37 /
+  // 1.23 s for the whole filter; on 1.5e6 keys of n = 100, k = 11 ... 14
+  // all took 5-7 ms).
   Coords C{};
   {
     int k = 0;
     if (U >= 64) {
       int lg = 0;
       while ((1u << (lg + 1)) <= U) ++lg;
-      k = (lg + 1) / 2 + 2;
+      k = (lg + 1) / 2 + 3;
     }
     k = k < kMaxC ? k : kMaxC;
     k = k < n ? k : n;
