@@ -218,8 +218,14 @@ __global__ __launch_bounds__(64 * kWaves, (waves_per_simd<CS, DBPW>())) void k_d
   float* sMV = reinterpret_cast<float*>(buf1 + kChunkU4);
   int* sLim = reinterpret_cast<int*>(reinterpret_cast<unsigned char*>(sMV) + (kMvLds ? mv_lds_bytes<DBPW>() : 0));
   // slice partial sums (forward, candidate) and the per-iteration exchange
-  __shared__ floatx4 redY[CS > 1 ? kWaves : 1][64];
-  __shared__ floatx4 redG[CS > 1 ? kWaves : 1][64];
+  // With LDS to spare (m and v not in LDS) the partial sums of consecutive
+  // row blocks alternate between two slots, so one barrier per row block
+  // both publishes them and the next basis chunk; otherwise a second barrier
+  // ends their reads before they are rewritten.
+  constexpr bool kOneBar = CS > 1 && !kMvLds;
+  constexpr int kRedSlots = kOneBar ? 2 : 1;
+  __shared__ floatx4 redY[kRedSlots][CS > 1 ? kWaves : 1][64];
+  __shared__ floatx4 redG[kRedSlots][CS > 1 ? kWaves : 1][64];
   __shared__ float xmu[kWaves][16], xcnt[kWaves][16];
   __shared__ int xflag[kWaves][16];
   __shared__ int xwave[kWaves];
@@ -445,21 +451,27 @@ __global__ __launch_bounds__(64 * kWaves, (waves_per_simd<CS, DBPW>())) void k_d
         }
         gx += g1;
       }
+      const int rs = kOneBar ? (ib & 1) : 0;
       if constexpr (CS > 1) {
+        if (descend) redY[rs][wid][lane] = acc;
+        if (needg) redG[rs][wid][lane] = gx;
+        if constexpr (kOneBar) {
+          // publishes the partial sums and the next row block (every read of
+          // this row block's chunk ended: its operands are in registers)
+          wait_vmem();
+        }
+        __syncthreads();
         // sum the slices' partial products in slice order (the same order in
         // every wave of the group, so all of them hold the same y and g)
-        if (descend) redY[wid][lane] = acc;
-        if (needg) redG[wid][lane] = gx;
-        __syncthreads();
         if (descend) {
-          acc = redY[gw0][lane];
+          acc = redY[rs][gw0][lane];
 #pragma unroll
-          for (int c = 1; c < CS; ++c) acc += redY[gw0 + c][lane];
+          for (int c = 1; c < CS; ++c) acc += redY[rs][gw0 + c][lane];
         }
         if (needg) {
-          gx = redG[gw0][lane];
+          gx = redG[rs][gw0][lane];
 #pragma unroll
-          for (int c = 1; c < CS; ++c) gx += redG[gw0 + c][lane];
+          for (int c = 1; c < CS; ++c) gx += redG[rs][gw0 + c][lane];
         }
       }
       {
@@ -483,10 +495,12 @@ __global__ __launch_bounds__(64 * kWaves, (waves_per_simd<CS, DBPW>())) void k_d
           wd |= ((uint32_t)(uint8_t)(int8_t)gv) << (8 * r);
         }
       }
-      // publishes the next row block, and (CS > 1) ends the reads of the
-      // partial sums before they are rewritten
-      wait_vmem();
-      __syncthreads();
+      if constexpr (!kOneBar) {
+        // publishes the next row block, and (CS > 1) ends the reads of the
+        // partial sums before they are rewritten
+        wait_vmem();
+        __syncthreads();
+      }
       // (stored after the wait: the next row block's wait for its loads then
       // finds the store long completed)
       if (needg && svalid && lead) srow[4 * ib + q] = wd;
