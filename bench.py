@@ -232,14 +232,19 @@ def bench_precision(args):
     for prec in ("fp32", "bf16"):
         fv = np.ascontiguousarray(F[prec].cpu().numpy()).view(np.dtype((np.void, ref.shape[1]))).ravel()
         res[prec]["recall"] = float(np.isin(rv, fv).sum() / max(1, rv.size))
+    n_, d_ = inst.n, B.shape[1]
+    roof32 = descent_roofline(n_, d_, N, T, res["fp32"]["descent_ms"])
+    rb = descent_roofline(n_, d_, N, T, res["bf16"]["descent_ms"], bf16_iters=T - T // 10)
+    res["bf16"]["roofline"] = {k: rb[k] for k in ("achieved", "peak", "frac")}
     _line("start-iterations/s of the descent, bf16 vs binary32 (extraction, precision comparison)",
           res["bf16"]["start_iterations_per_s"], "start-iterations/s", 1, 1, res["bf16"]["wall_ms"], "bf16+f32",
           {"workload": "quartic_m50_n400: m=50, n=400 (d=350), 4 nonzeros per row in +-1..+-5, separable "
                        "quartic f, box [-20,20]", "starts": N, "iters": T, "recall_starts": Nr},
           precision=res, speedup_bf16_over_fp32=res["fp32"]["wall_ms"] / res["bf16"]["wall_ms"],
-          roofline={"bound": "mfma", "kernel": res["fp32"]["kernel"], "achieved": res["fp32"]["tflops"],
-                    "peak": PEAK_FP32_MFMA, "unit": "TFLOP/s", "frac": res["fp32"]["tflops"] / PEAK_FP32_MFMA,
-                    "traffic": None, "note": "binary32 launch; the bf16 launch is reported in precision.bf16"})
+          roofline={"bound": "mfma", "kernel": res["fp32"]["kernel"], "achieved": roof32["achieved"],
+                    "peak": roof32["peak"], "unit": "TFLOP/s", "frac": roof32["frac"], "traffic": None,
+                    "peak_note": roof32["peak_note"],
+                    "note": "binary32 launch; the bf16 launch is reported in precision.bf16.roofline"})
     ctx.close()
 
 
@@ -361,12 +366,12 @@ def _serve_run(R, n_max=1000, rate=50.0, seed=5000):
 
 
 def bench_serve(args):
-    """Serving: the request stream of _serve_run at 50 requests/s, n up to 1000."""
+    """Serving: the request stream of _serve_run at 50 requests/s, n up to --n-max."""
     R = args.requests
-    r = _serve_run(R)
+    r = _serve_run(R, n_max=args.n_max)
     _line("requests/s at Poisson 50 req/s arrivals (p50/p99 solve latency beside)", r["completed_per_s"],
           "requests/s", R, 0, r["wall_s"] * 1e3 / R, "f32|bf16",
-          {"workload": "Poisson 50/s, n log-uniform [20,1000], m = round(0.2 n), A iid density 0.2 in +-1,+-2, "
+          {"workload": f"Poisson 50/s, n log-uniform [20,{args.n_max}], m = round(0.2 n), A iid density 0.2 in +-1,+-2, "
                        "quadratic (box [-5,5]) or quartic (box [-20,20]), fp32 or bf16, 16 n starts x 500 "
                        "iterations", "requests": R}, **{k: v for k, v in r.items() if k not in ("requests",)})
 
@@ -671,6 +676,7 @@ def main():
                     help="quartic: requests of the short serving leg reported beside (0: none)")
     ap.add_argument("--no-bf16-line", action="store_true", help="quartic: skip the bf16 + polish step")
     ap.add_argument("--requests", type=int, default=300, help="serve: number of requests")
+    ap.add_argument("--n-max", type=int, default=1000, help="serve: largest n of the request law")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device copy (a kernel of known traffic, for counter scaling)")
     args = ap.parse_args()
