@@ -334,7 +334,7 @@ __global__ void k_level_start(const int32_t* l1, uint32_t count, uint32_t* lo) {
 // g" digits that are 0 or the swapped digit; g enumerates these 2^z codes
 // (z = nonzeros of g on C) and tests only the keys of those buckets.  The
 // result is the same predicate as testing every pair.
-constexpr int kMaxC = 16;
+constexpr int kMaxC = 18;
 constexpr int kJoinThreads = 64;  // one wave
 struct Coords {
   int k;
@@ -477,9 +477,10 @@ __global__ __launch_bounds__(kJoinThreads) void k_pairs_join(const int8_t* keys,
   uint32_t* teb = tpos + tile_n;                                          // tile_n: bucket-order index | polarity
   __shared__ uint32_t lst_b[kListCap];       // bl offset of a non-empty candidate bucket | polarity
   __shared__ uint32_t lst_pre[kListCap + 1];  // sizes, then their exclusive prefix (total at [L])
-  // the item's candidate codes: code(j) = tcode[pol][0][j & 255] +
-  // tcode[pol][1][j >> 8] for subset j of the item's nonzero digits
-  __shared__ uint32_t tcode[2][2][256];
+  // the item's candidate codes: code(j) = tcode[pol][0][j & 63] +
+  // tcode[pol][1][(j >> 6) & 63] + tcode[pol][2][j >> 12] for subset j of
+  // the item's nonzero digits
+  __shared__ uint32_t tcode[2][3][64];
   const uint32_t lane = threadIdx.x;
   const uint32_t nwork = choff[ncode];
   for (uint32_t wk = blockIdx.x; wk < nwork; wk += gridDim.x) {
@@ -500,19 +501,19 @@ __global__ __launch_bounds__(kJoinThreads) void k_pairs_join(const int8_t* keys,
     for (int i = 0; i < kMaxC; ++i) z += dg[i] != 0;
     const uint32_t nsub = 1u << z;
     __syncthreads();  // the previous item's code tables are no longer read
-    for (uint32_t e = lane; e < 4u * 256u; e += kJoinThreads) {
-      const uint32_t pol = e >> 9, half = (e >> 8) & 1u, sub = e & 255u;
+    for (uint32_t e = lane; e < 6u * 64u; e += kJoinThreads) {
+      const uint32_t pol = e / 192u, part = (e / 64u) % 3u, sub = e & 63u;
       uint32_t code = 0;
       int bit = 0;
 #pragma unroll
       for (int i = 0; i < kMaxC; ++i) {
         if (dg[i]) {
-          const int hb8 = bit - 8 * (int)half;
-          if (hb8 >= 0 && hb8 < 8 && ((sub >> hb8) & 1u)) code += (uint32_t)((pol ? 3 - dg[i] : dg[i]) * C.pow3[i]);
+          const int b6 = bit - 6 * (int)part;
+          if (b6 >= 0 && b6 < 6 && ((sub >> b6) & 1u)) code += (uint32_t)((pol ? 3 - dg[i] : dg[i]) * C.pow3[i]);
           ++bit;
         }
       }
-      tcode[pol][half][sub] = code;
+      tcode[pol][part][sub] = code;
     }
     __syncthreads();
     const uint32_t e = gb + lane;
@@ -539,7 +540,7 @@ __global__ __launch_bounds__(kJoinThreads) void k_pairs_join(const int8_t* keys,
         if (j < 2 * nsub) {
           pol = j >= nsub ? 1u : 0u;
           const uint32_t sidx = j - pol * nsub;
-          const uint32_t code = tcode[pol][0][sidx & 255u] + tcode[pol][1][sidx >> 8];
+          const uint32_t code = tcode[pol][0][sidx & 63u] + tcode[pol][1][(sidx >> 6) & 63u] + tcode[pol][2][sidx >> 12];
           if ((bits[code >> 5] >> (code & 31u)) & 1u) {
             hb = off[code];
             he = off[code + 1];
@@ -723,9 +724,11 @@ hipError_t launch_filter(hipStream_t s, graver_ctx* ctx, int n, const int8_t* in
   // item enumerates up to 2 * 2^k codes, while the members it tests shrink
   // geometrically with k (for dense keys by about half per coordinate), so
   // k grows with log2 U: about log2(U) / 2 + 3, at most kMaxC (on 9.6e7 dense
-  // keys of n = 400, k = 13 / 14 / 15 / 16 measured 2.72 / 1.79 / 1.37 /
-  // 1.23 s for the whole filter; on 1.5e6 keys of n = 100, k = 11 ... 14
-  // all took 5-7 ms).
+  // keys of n = 400, k = 13 / 14 / 15 / 16 / 17 / 18 measured 2.72 / 1.79 /
+  // 1.37 / 1.23 / 1.18 / 1.55 s for the whole filter: past 16 the work
+  // items, chunks of one bucket, get smaller and each enumerates 2 * 2^k
+  // codes, and the code-indexed arrays grow as 3^k; on 1.5e6 keys of
+  // n = 100, k = 11 ... 14 all took 5-7 ms).
   Coords C{};
   {
     int k = 0;
