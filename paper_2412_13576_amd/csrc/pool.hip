@@ -36,55 +36,84 @@ hipError_t launch_pool_clear(hipStream_t s, PoolDev p) {
 // cross-workgroup ordering beyond the table word itself (on a multi-die
 // device, acquire/release at device scope would flush and invalidate the
 // per-die caches on every probe).
-//   probe : a thread per log row (all-zero rows are unused slots) probes the
+//   probe : a lane per log row (all-zero rows are unused slots; rows staged
+//           in LDS a wave tile at a time) probes the
 //           table with relaxed device-scope atomics; an empty slot is claimed
 //           by a compare-and-swap with the entry (tag, kLogRow | row), so the
 //           entry points at the log row itself.  A tag match is compared
 //           against the log row or the pool key it points at, both written
 //           by earlier launches.
-//   commit: a thread per table slot moves every claimed log row into the
-//           pool (indices taken once per wave) and rewrites the entry to
-//           (tag, pool index).
+//   commit: a lane per table slot finds the claimed log rows, the wave
+//           copies them into the pool together (indices taken once per wave)
+//           and each lane rewrites its entry to (tag, pool index).
 constexpr uint32_t kLogRow = 0x80000000u;
 
-__global__ void k_log_probe(LogDev log, PoolDev pool) {
+// A wave takes a tile of consecutive log rows (at most kProbeTileBytes),
+// copies it to LDS with coalesced loads, and then each lane probes with its
+// own row read from LDS.  (With a lane reading its row word by word from
+// global memory, a wave touches 64 rows' cache lines per load and the lines
+// were fetched again and again: 12x the log's bytes.)
+constexpr int kProbeWaves = 4;
+constexpr int kProbeTileBytes = 8192;
+
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ __launch_bounds__(64 * kProbeWaves) void k_log_probe(LogDev log, PoolDev pool) {
+  extern __shared__ __align__(16) uint64_t ptile[];  // kProbeWaves tiles of trows x stride bytes
   const uint32_t nrows = min(*log.count, log.cap);
   const int nwords = log.stride / 8;
-  for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < nrows; r += gridDim.x * blockDim.x) {
-    const uint64_t* key = reinterpret_cast<const uint64_t*>(log.rows + (size_t)r * log.stride);
-    bool nz = false;
-    for (int w = 0; w < nwords; ++w) nz |= key[w] != 0;
-    if (!nz) continue;
-    const uint64_t h = hash_key_words(key, nwords);
-    const uint32_t tag = (uint32_t)(h >> 32) | 0x80000000u;
-    uint64_t slot = h & pool.tmask;
-    bool settled = false;
-    for (int it = 0; it < kMaxProbeIters && !settled; ++it) {
-      uint64_t e = __hip_atomic_load(&pool.table[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (e == 0) {
-        uint64_t expected = 0;
-        const uint64_t mine = ((uint64_t)tag << 32) | kLogRow | r;
-        if (__hip_atomic_compare_exchange_strong(&pool.table[slot], &expected, mine, __ATOMIC_RELAXED,
-                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-          settled = true;
-          continue;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int trows = min(64, kProbeTileBytes / log.stride);
+  uint64_t* tile = ptile + (size_t)wid * trows * nwords;
+  const uint64_t nwaves = (uint64_t)gridDim.x * kProbeWaves;
+  for (uint64_t r0 = ((uint64_t)blockIdx.x * kProbeWaves + wid) * trows; r0 < nrows; r0 += nwaves * trows) {
+    const int rows = (int)min((uint64_t)trows, nrows - r0);
+    const uint64_t* src = reinterpret_cast<const uint64_t*>(log.rows + r0 * log.stride);
+    for (int w = lane; w < rows * nwords; w += 64) tile[w] = src[w];
+    wave_sync_lds();
+    if (lane < rows) {
+      const uint32_t r = (uint32_t)r0 + (uint32_t)lane;
+      const uint64_t* key = tile + (size_t)lane * nwords;
+      bool nz = false;
+      for (int w = 0; w < nwords; ++w) nz |= key[w] != 0;
+      if (nz) {
+        const uint64_t h = hash_key_words(key, nwords);
+        const uint32_t tag = (uint32_t)(h >> 32) | 0x80000000u;
+        uint64_t slot = h & pool.tmask;
+        bool settled = false;
+        for (int it = 0; it < kMaxProbeIters && !settled; ++it) {
+          uint64_t e = __hip_atomic_load(&pool.table[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (e == 0) {
+            uint64_t expected = 0;
+            const uint64_t mine = ((uint64_t)tag << 32) | kLogRow | r;
+            if (__hip_atomic_compare_exchange_strong(&pool.table[slot], &expected, mine, __ATOMIC_RELAXED,
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+              settled = true;
+              continue;
+            }
+            e = expected;  // the entry another thread just wrote
+          }
+          if ((uint32_t)(e >> 32) == tag) {
+            const uint32_t lo = (uint32_t)e;
+            const uint64_t* other = reinterpret_cast<const uint64_t*>(
+                (lo & kLogRow) ? log.rows + (size_t)(lo & ~kLogRow) * log.stride : pool.keys + (size_t)lo * pool.stride);
+            bool same = true;
+            for (int w = 0; w < nwords && same; ++w) same = other[w] == key[w];
+            if (same) {
+              settled = true;
+              continue;
+            }
+          }
+          slot = (slot + 1) & pool.tmask;
         }
-        e = expected;  // the entry another thread just wrote
+        if (!settled) atomicOr(&pool.count[2], 1u);
       }
-      if ((uint32_t)(e >> 32) == tag) {
-        const uint32_t lo = (uint32_t)e;
-        const uint64_t* other = reinterpret_cast<const uint64_t*>(
-            (lo & kLogRow) ? log.rows + (size_t)(lo & ~kLogRow) * log.stride : pool.keys + (size_t)lo * pool.stride);
-        bool same = true;
-        for (int w = 0; w < nwords && same; ++w) same = other[w] == key[w];
-        if (same) {
-          settled = true;
-          continue;
-        }
-      }
-      slot = (slot + 1) & pool.tmask;
     }
-    if (!settled) atomicOr(&pool.count[2], 1u);
+    wave_sync_lds();  // every lane's reads of the tile end before it is refilled
   }
 }
 
@@ -115,19 +144,46 @@ __global__ void k_log_commit(LogDev log, PoolDev pool) {
     const uint64_t e = slot < tsize ? pool.table[slot] : 0ull;
     const bool pending = e != 0 && ((uint32_t)e & kLogRow) != 0;
     const uint64_t wm = __ballot(pending);
-    if (pending) {
-      const uint32_t idx =
-          base + __builtin_amdgcn_mbcnt_hi((uint32_t)(wm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)wm, 0u));
-      if (idx >= pool.cap) {
-        atomicOr(&pool.count[1], 1u);
-      } else {
-        const uint64_t* src =
-            reinterpret_cast<const uint64_t*>(log.rows + (size_t)((uint32_t)e & ~kLogRow) * log.stride);
-        uint64_t* dst = reinterpret_cast<uint64_t*>(pool.keys + (size_t)idx * pool.stride);
-        for (int w = 0; w < nwords; ++w) dst[w] = src[w];
-        pool.table[slot] = (e & 0xFFFFFFFF00000000ull) | idx;
+    const uint32_t idx =
+        base + __builtin_amdgcn_mbcnt_hi((uint32_t)(wm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)wm, 0u));
+    const bool fits = pending && idx < pool.cap;
+    if (pending && !fits) atomicOr(&pool.count[1], 1u);
+    // the wave copies the claimed rows together, four rows per round trip,
+    // each row's words spread over the lanes (coalesced loads and stores)
+    uint64_t cm = __ballot(fits);
+    while (cm != 0) {
+      uint32_t srow[4], drow[4];
+      int nr = 0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (cm == 0) break;
+        const int l = __builtin_ctzll(cm);
+        cm &= cm - 1;
+        srow[u] = (uint32_t)__shfl((int)((uint32_t)e & ~kLogRow), l, 64);
+        drow[u] = (uint32_t)__shfl((int)idx, l, 64);
+        ++nr;
+      }
+      for (int w0 = 0; w0 < nwords; w0 += 128) {
+        uint64_t v[4][2];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int w = w0 + lane + 64 * h;
+            if (u < nr && w < nwords)
+              v[u][h] = reinterpret_cast<const uint64_t*>(log.rows + (size_t)srow[u] * log.stride)[w];
+          }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int w = w0 + lane + 64 * h;
+            if (u < nr && w < nwords)
+              reinterpret_cast<uint64_t*>(pool.keys + (size_t)drow[u] * pool.stride)[w] = v[u][h];
+          }
       }
     }
+    if (fits) pool.table[slot] = (e & 0xFFFFFFFF00000000ull) | idx;
     base += (uint32_t)__popcll(wm);
   }
 }
@@ -136,7 +192,9 @@ hipError_t launch_log_insert(hipStream_t s, LogDev log, PoolDev pool) {
   unsigned blocks = (unsigned)((log.cap + 255) / 256);
   if (blocks > 8192) blocks = 8192;
   if (blocks == 0) blocks = 1;
-  hipLaunchKernelGGL(k_log_probe, dim3(blocks), dim3(256), 0, s, log, pool);
+  const int trows = std::min(64, kProbeTileBytes / log.stride);
+  hipLaunchKernelGGL(k_log_probe, dim3(blocks), dim3(64 * kProbeWaves),
+                     (size_t)kProbeWaves * trows * log.stride, s, log, pool);
   const uint64_t tsize = pool.tmask + 1;
   const uint64_t waves = (tsize + 64 * kCommitIters - 1) / (64 * kCommitIters);
   hipLaunchKernelGGL(k_log_commit, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, log, pool);
