@@ -74,11 +74,22 @@ __global__ __launch_bounds__(kTileRows) void k_canon(const int8_t* in, int64_t c
   for (int w = threadIdx.x; w < words; w += blockDim.x) o64[w] = t64[w];
 }
 
+// (64 bytes per round trip: rows with equal prefixes often share long runs)
 __device__ __forceinline__ bool rows_equal(const int8_t* keys, int stride, uint32_t a, uint32_t b) {
-  const uint64_t* ka = reinterpret_cast<const uint64_t*>(keys + (size_t)a * stride);
-  const uint64_t* kb = reinterpret_cast<const uint64_t*>(keys + (size_t)b * stride);
-  for (int w = 0; w < stride / 8; ++w)
-    if (ka[w] != kb[w]) return false;
+  const uint4* ka = reinterpret_cast<const uint4*>(keys + (size_t)a * stride);
+  const uint4* kb = reinterpret_cast<const uint4*>(keys + (size_t)b * stride);
+  const int nc = stride / 16;
+  for (int c0 = 0; c0 < nc; c0 += 4) {
+    uint32_t diff = 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (c0 + u < nc) {
+        const uint4 x = ka[c0 + u], y = kb[c0 + u];
+        diff |= (x.x ^ y.x) | (x.y ^ y.y) | (x.z ^ y.z) | (x.w ^ y.w);
+      }
+    }
+    if (diff) return false;
+  }
   return true;
 }
 

@@ -294,11 +294,27 @@ __device__ __forceinline__ bool pair_greater(const int8_t* keys, int stride, uin
   const bool va = a < count, vb = b < count;
   if (!va || !vb) return !va && (vb || a > b);
   if (pa != pb) return pa > pb;
-  const uint64_t* ka = reinterpret_cast<const uint64_t*>(keys + (size_t)a * stride);
-  const uint64_t* kb = reinterpret_cast<const uint64_t*>(keys + (size_t)b * stride);
-  for (int w = 1; w < stride / 8; ++w) {
-    const uint64_t x = ka[w], y = kb[w];
-    if (x != y) return order_word(x) > order_word(y);
+  // tied prefixes are common (rows of one descent trajectory share long
+  // runs of leading components): compare 64 bytes per round trip, four
+  // 16-byte loads per row in flight
+  const uint4* ka = reinterpret_cast<const uint4*>(keys + (size_t)a * stride);
+  const uint4* kb = reinterpret_cast<const uint4*>(keys + (size_t)b * stride);
+  const int nc = stride / 16;
+  for (int c0 = 0; c0 < nc; c0 += 4) {
+    uint4 x[4], y[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const bool in = c0 + u < nc;
+      x[u] = in ? ka[c0 + u] : make_uint4(0, 0, 0, 0);
+      y[u] = in ? kb[c0 + u] : make_uint4(0, 0, 0, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint64_t x0 = (uint64_t)x[u].x | ((uint64_t)x[u].y << 32), y0 = (uint64_t)y[u].x | ((uint64_t)y[u].y << 32);
+      if (x0 != y0) return order_word(x0) > order_word(y0);
+      const uint64_t x1 = (uint64_t)x[u].z | ((uint64_t)x[u].w << 32), y1 = (uint64_t)y[u].z | ((uint64_t)y[u].w << 32);
+      if (x1 != y1) return order_word(x1) > order_word(y1);
+    }
   }
   return a > b;
 }
