@@ -480,9 +480,13 @@ __global__ __launch_bounds__(kJoinThreads) void k_pairs_join(const int8_t* keys,
                                                            const ulonglong2* __restrict__ bfirst, Coords C,
                                                            const uint32_t* __restrict__ choff,
                                                            const uint32_t* __restrict__ owner, uint32_t ncode,
-                                                           const uint32_t* __restrict__ bits, int tile_n,
-                                                           uint32_t* alive) {
+                                                           const uint32_t* __restrict__ bits, uint32_t* alive) {
   extern __shared__ uint64_t smem_join[];
+  // a tile holds one member per lane (small tiles keep more one-wave blocks
+  // resident and let an item stop sooner once its keys are dead: on the
+  // quartic headline's keys 32 / 64 / 96 / 128 / 256 / 512 / 1024 members
+  // gave 0.94 / 0.92 / 0.92 / 0.97 / 1.08 / 1.45 / 2.12 s for the whole filter)
+  constexpr uint32_t tile_n = kJoinThreads;
   ulonglong2* tfirst = reinterpret_cast<ulonglong2*>(smem_join);          // tile_n: first positive / negative words
   uint32_t* tpos = reinterpret_cast<uint32_t*>(tfirst + tile_n);          // tile_n: position
   uint32_t* teb = tpos + tile_n;                                          // tile_n: bucket-order index | polarity
@@ -597,24 +601,35 @@ __global__ __launch_bounds__(kJoinThreads) void k_pairs_join(const int8_t* keys,
         if (lane == 0) lst_pre[L] = total;
       }
       __syncthreads();
+      // this lane's member of a tile: list entry, then its first mask words
+      // (polarity applied: -h below g is tested as h with its sign words
+      // swapped), position and bucket-order index; read one tile ahead so
+      // the loads are in flight while the current tile is tested
+      ulonglong2 nf = make_ulonglong2(~0ull, ~0ull);
+      uint32_t npos = 0xFFFFFFFFu, neb = 0;
+      auto fetch = [&](uint32_t q) {
+        if (q >= total) return;
+        uint32_t a = 0, b = L - 1;  // last list entry whose prefix is <= q (prefixes strictly increase)
+        while (a < b) {
+          const uint32_t mid = (a + b + 1) / 2;
+          if (lst_pre[mid] <= q) a = mid; else b = mid - 1;
+        }
+        const uint32_t hb = lst_b[a];
+        const uint32_t eb = (hb & ~kPolBit) + (q - lst_pre[a]);
+        const ulonglong2 f = bfirst[eb];
+        nf = (hb & kPolBit) ? make_ulonglong2(f.y, f.x) : f;
+        npos = bl[eb];
+        neb = eb | (hb & kPolBit);
+      };
+      fetch(lane);
       for (uint32_t t0 = 0; t0 < total; t0 += tile_n) {
         if (__ballot(!idle && !dead) == 0) break;
-        const uint32_t cnt = min((uint32_t)tile_n, total - t0);
+        const uint32_t cnt = min(tile_n, total - t0);
         __syncthreads();  // the previous tile is no longer read
-        for (uint32_t t = lane; t < cnt; t += kJoinThreads) {
-          const uint32_t q = t0 + t;
-          uint32_t a = 0, b = L - 1;  // last list entry whose prefix is <= q (prefixes strictly increase)
-          while (a < b) {
-            const uint32_t mid = (a + b + 1) / 2;
-            if (lst_pre[mid] <= q) a = mid; else b = mid - 1;
-          }
-          const uint32_t hb = lst_b[a];
-          const uint32_t eb = (hb & ~kPolBit) + (q - lst_pre[a]);
-          const ulonglong2 f = bfirst[eb];
-          // -h below g is tested as h with its sign words swapped
-          tfirst[t] = (hb & kPolBit) ? make_ulonglong2(f.y, f.x) : f;
-          tpos[t] = bl[eb];
-          teb[t] = eb | (hb & kPolBit);
+        if (lane < cnt) {
+          tfirst[lane] = nf;
+          tpos[lane] = npos;
+          teb[lane] = neb;
         }
         // pad the tile to a multiple of 4 members that never match
         for (uint32_t t = cnt + lane; t < ((cnt + 3u) & ~3u); t += kJoinThreads) {
@@ -622,6 +637,7 @@ __global__ __launch_bounds__(kJoinThreads) void k_pairs_join(const int8_t* keys,
           tfirst[t] = make_ulonglong2(~0ull, ~0ull);
         }
         __syncthreads();
+        fetch(t0 + tile_n + lane);
         if (idle || dead) continue;
         // Fast test on the first 64 coordinates of the sign masks, four
         // members at a time; the other words and the magnitudes are read only
@@ -830,16 +846,11 @@ hipError_t launch_filter(hipStream_t s, graver_ctx* ctx, int n, const int8_t* in
   if (!bits) return hipSuccess;
   hipLaunchKernelGGL(k_bucket_bits, dim3((ncode / 32 + 1 + 255) / 256), dim3(256), 0, s, hist, ncode, bits);
   HIP_RET(hipGetLastError());
-  // members per tile (a multiple of 4): 24 bytes each in LDS.  Small tiles
-  // keep more one-wave blocks resident and let an item stop sooner once its
-  // keys are dead (on the quartic headline's keys: 32 / 64 / 96 / 128 / 256 /
-  // 512 / 1024 members gave 0.94 / 0.92 / 0.92 / 0.97 / 1.08 / 1.45 / 2.12 s
-  // for the whole filter)
-  const int tile_n = 64;
-  const size_t jshm = (size_t)tile_n * (sizeof(ulonglong2) + 2 * sizeof(uint32_t));
+  // one tile member per lane, 24 bytes each in LDS
+  const size_t jshm = (size_t)kJoinThreads * (sizeof(ulonglong2) + 2 * sizeof(uint32_t));
   const unsigned jgrid = (unsigned)(max_items < (1u << 20) ? max_items : (1u << 20));
   hipLaunchKernelGGL(k_pairs_join, dim3(jgrid), dim3(kJoinThreads), jshm, s, canon, stride, n, W, mskb, lo, boff, bl,
-                     bmsk, reinterpret_cast<const ulonglong2*>(bfirst), C, choff, owner, ncode, bits, tile_n, alive);
+                     bmsk, reinterpret_cast<const ulonglong2*>(bfirst), C, choff, owner, ncode, bits, alive);
   HIP_RET(hipGetLastError());
   // survivors back in lexicographic order: flags to lex positions, then compact uniq
   hipLaunchKernelGGL(k_scatter_flags, dim3(u256), dim3(256), 0, s, idx, alive, U, flag);
