@@ -47,6 +47,15 @@ typedef enum {
   GRAVER_BF16 = 2  /* contractions on bf16 MFMA, fp32 accumulate, fp32 polish */
 } graver_precision;
 
+/* How a binary32 descent forms the products with B (graver_extract_params.form). */
+typedef enum {
+  GRAVER_FORM_AUTO = 0,   /* sparse row lists when B's pay off (see below), else matrix cores */
+  GRAVER_FORM_DENSE = 1,  /* matrix cores (MFMA) for every product                 */
+  GRAVER_FORM_SPARSE = 2  /* row lists of B's nonzeros: gathers and exact scatter-adds,
+                             one start per wavefront; GRAVER_FP32 only, n <= 1024,
+                             d <= 1024, at most 128 row-list entries per lane       */
+} graver_form;
+
 typedef enum {
   GRAVER_F_QUADRATIC = 1,     /* f(x) = x^T Q x + c^T x, Q symmetric n x n  */
   GRAVER_F_SEPARABLE_POLY = 2 /* f(x) = sum_i sum_{k=0..deg} coef[i*(deg+1)+k] x_i^k */
@@ -95,6 +104,13 @@ typedef struct {
   int32_t any_order; /* 0: keys sorted lexicographically (deterministic order);
                         1: keys in the pool's order (the same set; for callers
                         that filter next, which sorts anyway)               */
+  int32_t form;      /* graver_form.  AUTO takes the sparse form for a
+                        GRAVER_FP32 call that the large matrix-core kernel
+                        would run when B's padded row lists hold at most an
+                        eighth of the n x d products.  The sparse form's exact
+                        range is |round(z_j)| <= floor(2^24 / max row l1 of B)
+                        (the small matrix-core kernel's); the large kernel's
+                        is |round(z_j)| <= 256                               */
 } graver_extract_params;
 
 /* Optional descent state, device pointers to N x d binary64 arrays.  With
@@ -116,6 +132,8 @@ typedef struct {
   double ms_init, ms_descent, ms_verify, ms_sort; /* device time per phase  */
   int32_t tile_slices;      /* large-basis kernel: waves per start group     */
   int32_t tile_blocks;      /* and 16-column blocks per wave (0 otherwise)    */
+  int32_t row_entries;      /* sparse form: row-list entries per lane (0 otherwise) */
+  int32_t row_slots;        /* and its slots of 64 rows (0 otherwise)           */
 } graver_extract_stats;
 
 typedef struct {

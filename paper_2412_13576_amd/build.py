@@ -30,6 +30,7 @@ SOURCES = {
     "descent_fp64.hip": ["-ffp-contract=off"],
     "descent_f32.hip": ["-ffp-contract=fast"],
     "descent_big.hip": ["-ffp-contract=fast"],
+    "descent_sparse.hip": ["-ffp-contract=fast"],
     "filter.hip": [],
     "augment.hip": ["-ffp-contract=off"],
     "extract.cpp": ["-x", "hip"],

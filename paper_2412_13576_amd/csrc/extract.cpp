@@ -23,13 +23,14 @@
 #include <string>
 #include <vector>
 
+#include "descent_sparse.h"
 #include "graver_internal.h"
 
 namespace graver {
 
 namespace {
 
-enum JobKind { JOB_FP64, JOB_SMALL, JOB_BIG };
+enum JobKind { JOB_FP64, JOB_SMALL, JOB_BIG, JOB_SPARSE };
 
 struct Job {
   // call arguments
@@ -68,6 +69,8 @@ struct Job {
   size_t sbytes = 0;
   int bf16_total = 0;
   int done = 0;
+  SparseImage sp;  // row lists of B (sparse form)
+  uint32_t *sp_ent = nullptr, *sp_row = nullptr;
 };
 
 struct TileCache {
@@ -177,6 +180,12 @@ graver_status job_setup(graver_ctx* ctx, Job& j, bool force_big, bool autotune) 
         for (int k = 0; k < n; ++k) s += (__int128)hA[(size_t)i * n + k] * hB[(size_t)k * d + c];
         if (s != 0) return set_error(GRAVER_E_NOT_KERNEL, "A B != 0: B is not a kernel basis");
       }
+    if (prm->form < GRAVER_FORM_AUTO || prm->form > GRAVER_FORM_SPARSE) return set_error(GRAVER_E_INVALID, "unknown form");
+    if (prm->form == GRAVER_FORM_SPARSE && prm->precision != GRAVER_FP32)
+      return set_error(GRAVER_E_INVALID, "the sparse form runs binary32 descents only");
+    if (prm->precision == GRAVER_FP32 && prm->form != GRAVER_FORM_DENSE &&
+        !sparse_image_build(n, d, hB.data(), j.hl.data(), j.hu.data(), j.sp) && prm->form == GRAVER_FORM_SPARSE)
+      return set_error(GRAVER_E_INVALID, "B does not fit the sparse form (n, d <= 1024, at most 128 row-list entries per lane)");
   }
 
   hipStream_t s = ctx->stream;
@@ -290,10 +299,13 @@ graver_status job_setup(graver_ctx* ctx, Job& j, bool force_big, bool autotune) 
     return GRAVER_OK;
   }
 
-  const bool small = !force_big && descent_f32_supported(n, d);
-  if (!small && !descent_big_supported(n, d))
+  const bool small0 = !force_big && descent_f32_supported(n, d);
+  // the sparse form: asked for, or automatic where the large kernel would run
+  const bool sparse = j.sp.nc > 0 && (prm->form == GRAVER_FORM_SPARSE || (!small0 && sparse_form_pays(j.sp, n, d)));
+  const bool small = small0 && !sparse;
+  if (!small && !sparse && !descent_big_supported(n, d))
     return set_error(GRAVER_E_INVALID, "the MFMA descent supports n <= 1024 and d <= 1024");
-  j.kind = small ? JOB_SMALL : JOB_BIG;
+  j.kind = sparse ? JOB_SPARSE : (small ? JOB_SMALL : JOB_BIG);
   // |B_ij| <= 256 makes every bf16 operand exact; row l1 norms bound the
   // exact range of the candidate map.
   int* rowl1 = (int*)W(ctx, j, WS_MISC, 64, &st);
@@ -313,10 +325,21 @@ graver_status job_setup(graver_ctx* ctx, Job& j, bool force_big, bool autotune) 
   if (hrow[1] > 256)
     return set_error(GRAVER_E_INVALID, "the MFMA descent needs |B_ij| <= 256 (exact bf16 operands)");
   // large bases: candidates B r with |r_j| <= 256 must stay exact in fp32
-  if (!small && (int64_t)hrow[0] * 256 >= (int64_t)1 << 24)
+  if (j.kind == JOB_BIG && (int64_t)hrow[0] * 256 >= (int64_t)1 << 24)
     return set_error(GRAVER_E_INVALID, "the MFMA descent needs every row l1 norm of B below 65536");
   j.zrange = (float)std::min(1073741824.0, std::floor(16777216.0 / std::max(hrow[0], 1)));
-  if (!small) {
+  if (sparse) {
+    j.sp_ent = (uint32_t*)W(ctx, j, WS_MF_B, j.sp.ent.size() * sizeof(uint32_t), &st);
+    if (!j.sp_ent) return st;
+    j.sp_row = (uint32_t*)W(ctx, j, WS_MF_BT, j.sp.row.size() * sizeof(uint32_t), &st);
+    if (!j.sp_row) return st;
+    HIP_TRY(hipMemcpyAsync(j.sp_ent, j.sp.ent.data(), j.sp.ent.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s),
+            "row lists");
+    HIP_TRY(hipMemcpyAsync(j.sp_row, j.sp.row.data(), j.sp.row.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s),
+            "row slots");
+    j.stt.row_entries = j.sp.ew;
+    j.stt.row_slots = j.sp.nc;
+  } else if (!small) {
     j.kscr = (int8_t*)W(ctx, j, WS_KEYSCRATCH, ((size_t)N + 64) * pool.stride, &st);
     if (!j.kscr) return st;
     j.sh = big_shape_default(d);
@@ -379,12 +402,12 @@ graver_status job_setup(graver_ctx* ctx, Job& j, bool force_big, bool autotune) 
     if (!j.img) return st;
     HIP_TRY(launch_big_pack(s, n, d, j.sh, prob->B, j.img), "pack basis");
   }
-  j.DBlay = small ? (d + 15) / 16 : j.sh.cs * j.sh.dbpw;
-  if (!small) {
+  j.DBlay = small || sparse ? (d + 15) / 16 : j.sh.cs * j.sh.dbpw;
+  if (j.kind == JOB_BIG) {
     j.stt.tile_slices = j.sh.cs;
     j.stt.tile_blocks = j.sh.dbpw;
   }
-  const size_t sfloats = small ? f32_state_floats(n, d, N) : big_state_floats(j.sh, N);
+  const size_t sfloats = small || sparse ? f32_state_floats(n, d, N) : big_state_floats(j.sh, N);
   j.fstate = (float*)W(ctx, j, WS_MF_STATE, sfloats * sizeof(float), &st);
   if (!j.fstate) return st;
   HIP_TRY(launch_state_io_db(s, d, j.DBlay, N, j.fstate, j.z, j.mm, j.vv, 1), "state in");
@@ -430,7 +453,7 @@ graver_status job_descend(graver_ctx* ctx, Job& j, int until) {
   const bool small = j.kind == JOB_SMALL;
   int chunk = until - j.done;
   void* ddesc = nullptr;
-  if (!small) {
+  if (j.kind == JOB_BIG) {
     ddesc = W(ctx, j, WS_BIG_DESC, 4096, &st);
     if (!ddesc) return st;
   }
@@ -450,6 +473,10 @@ graver_status job_descend(graver_ctx* ctx, Job& j, int until) {
     EventTimer tm(s);
     if (small) {
       HIP_TRY(launch_descent_f32(s, dc, j.Bp, j.BTp, j.fstate, j.pool, j.counters, j.zrange), "descent mfma");
+    } else if (j.kind == JOB_SPARSE) {
+      HIP_TRY(launch_descent_sparse(s, dc, j.sp, j.sp_ent, j.sp_row, j.fstate, (int64_t)(j.sbytes / sizeof(float) / 3),
+                                    j.counters, j.zrange),
+              "descent (sparse form)");
     } else {
       BigJob bj{dc, j.img, j.fstate, j.kscr, j.counters};
       int64_t blocks = 0;

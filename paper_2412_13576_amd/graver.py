@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libgraver.so")
 
 GRAVER_FP64, GRAVER_FP32, GRAVER_BF16 = 0, 1, 2
 GRAVER_F_QUADRATIC, GRAVER_F_SEPARABLE_POLY = 1, 2
+GRAVER_FORM_AUTO, GRAVER_FORM_DENSE, GRAVER_FORM_SPARSE = 0, 1, 2
 (GRAVER_OK, GRAVER_E_INVALID, GRAVER_E_INFEASIBLE_START, GRAVER_E_NOT_KERNEL, GRAVER_E_OVERFLOW,
  GRAVER_E_POOL_FULL, GRAVER_E_NOMEM, GRAVER_E_DEVICE, GRAVER_E_CAPACITY, GRAVER_E_CANCELLED) = range(0, -10, -1)
 STATUS = {0: "OK", -1: "E_INVALID", -2: "E_INFEASIBLE_START", -3: "E_NOT_KERNEL",
@@ -55,7 +56,7 @@ class ExtractParams(C.Structure):
                 ("lambda1", C.c_double), ("lambda2", C.c_double),
                 ("init_mode", C.c_int32), ("t0", C.c_int32), ("polish_iters", C.c_int32),
                 ("collect", C.c_int32), ("seed", C.c_uint64), ("first_start", C.c_int64),
-                ("pool_capacity", C.c_int64), ("any_order", C.c_int32)]
+                ("pool_capacity", C.c_int64), ("any_order", C.c_int32), ("form", C.c_int32)]
 
 
 class State(C.Structure):
@@ -67,7 +68,8 @@ class ExtractStats(C.Structure):
                 ("inbox_events", C.c_int64), ("unique", C.c_int64), ("verified", C.c_int64),
                 ("out_of_range", C.c_int64), ("ms_init", C.c_double), ("ms_descent", C.c_double),
                 ("ms_verify", C.c_double), ("ms_sort", C.c_double),
-                ("tile_slices", C.c_int32), ("tile_blocks", C.c_int32)]
+                ("tile_slices", C.c_int32), ("tile_blocks", C.c_int32),
+                ("row_entries", C.c_int32), ("row_slots", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -274,9 +276,10 @@ class DeviceProblem:
 
 def extract_params(n_starts, iters, precision=GRAVER_FP64, init_mode=0, seed=0, t0=0,
                    pool_capacity=1 << 20, collect=1, lr=0.003, beta1=0.9, beta2=0.999, eps=1e-8,
-                   lambda1=0.85, lambda2=1.0, polish_iters=0, first_start=0, any_order=False) -> ExtractParams:
+                   lambda1=0.85, lambda2=1.0, polish_iters=0, first_start=0, any_order=False,
+                   form=0) -> ExtractParams:
     return ExtractParams(n_starts, iters, precision, lr, beta1, beta2, eps, lambda1, lambda2, init_mode,
-                         t0, polish_iters, collect, seed, first_start, pool_capacity, int(any_order))
+                         t0, polish_iters, collect, seed, first_start, pool_capacity, int(any_order), int(form))
 
 
 def extract(ctx: Context, prob: DeviceProblem, params: ExtractParams, state=None, keys_cap=None):

@@ -53,26 +53,34 @@ def _inst(name):
     return _cache[name]
 
 
+def _pf(G, prec):
+    """(precision, form) of a case name: binary32 in the form the library
+    picks (the sparse form on the quartic basis), binary32 on matrix cores,
+    or bf16 on matrix cores."""
+    return {"fp32": (G.GRAVER_FP32, G.GRAVER_FORM_AUTO), "fp32-dense": (G.GRAVER_FP32, G.GRAVER_FORM_DENSE),
+            "bf16": (G.GRAVER_BF16, G.GRAVER_FORM_AUTO)}[prec]
+
+
 def _dev(x):
     return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
 
 
 @pytest.mark.parametrize("name", IDS)
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("prec", ["fp32", "fp32-dense", "bf16"])
 def test_wide_teacher_forced_single_step(G, ctx, name, prec):
     inst, B = _inst(name)
     _say("wide teacher-forced", name, prec)
     N = 50                      # ragged: the last start group holds 2 starts
     z0 = W.gaussian_starts(N, B.shape[1], 2.0, 77)
     prob = G.DeviceProblem.from_numpy(inst.A, inst.b, inst.l, inst.u, B)
-    precision = G.GRAVER_FP32 if prec == "fp32" else G.GRAVER_BF16
+    precision, form = _pf(G, prec)
     for t_teacher in (0, 25):
         z, mm, vv, _ = (S.descend(B, z0, t_teacher, P_) if t_teacher
                         else (z0, np.zeros_like(z0), np.zeros_like(z0), 0))
         zo, mo, _, _ = S.descend(B, z, 1, P_, m0=mm, v0=vv, t0=t_teacher)
         st = {"z": _dev(z), "m": _dev(mm), "v": _dev(vv)}
-        G.extract(ctx, prob, G.extract_params(N, 1, precision=precision, init_mode=1, t0=t_teacher, collect=0),
-                  state=st)
+        G.extract(ctx, prob, G.extract_params(N, 1, precision=precision, init_mode=1, t0=t_teacher, collect=0,
+                                              form=form), state=st)
         err, flagged = _check_step(B, z, mm, vv, t_teacher + 1, st["z"].cpu().numpy(), zo)
         _say("wide teacher-forced", name, prec, t_teacher, "max err", float(err.max()), "kink starts", flagged)
         assert np.median(_relerr(st["m"].cpu().numpy(), mo)) <= TOL
@@ -130,7 +138,7 @@ def test_wide_fp64_sets_equal_oracle(G, ctx):
     _say("wide fp64 vs oracle", "keys", len(got))
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("prec", ["fp32", "fp32-dense", "bf16"])
 def test_wide_resume_and_overflow_replay(G, ctx, prec):
     """Chunked calls reproduce one long call bit for bit (the bf16 form is
     resumed inside its bf16 phase), and a small pool capacity (log
@@ -138,24 +146,27 @@ def test_wide_resume_and_overflow_replay(G, ctx, prec):
     inst, B = _inst("quartic_n400_d350")
     _say("wide resume / replay", prec)
     N = 1000
-    precision = G.GRAVER_FP32 if prec == "fp32" else G.GRAVER_BF16
+    precision, form = _pf(G, prec)
     z0 = W.gaussian_starts(N, B.shape[1], 0.3, 79)
     prob = G.DeviceProblem.from_numpy(inst.A, inst.b, inst.l, inst.u, B)
     zero = lambda: torch.zeros((N, B.shape[1]), dtype=torch.float64, device="cuda")
     st1 = {"z": _dev(z0), "m": zero(), "v": zero()}
-    G.extract(ctx, prob, G.extract_params(N, 30, precision=precision, init_mode=1, collect=0), state=st1)
-    G.extract(ctx, prob, G.extract_params(N, 20, precision=precision, init_mode=1, t0=30, collect=0), state=st1)
+    G.extract(ctx, prob, G.extract_params(N, 30, precision=precision, init_mode=1, collect=0, form=form), state=st1)
+    G.extract(ctx, prob, G.extract_params(N, 20, precision=precision, init_mode=1, t0=30, collect=0, form=form),
+              state=st1)
     st2 = {"z": _dev(z0), "m": zero(), "v": zero()}
-    G.extract(ctx, prob, G.extract_params(N, 50, precision=precision, init_mode=1, collect=0), state=st2)
+    G.extract(ctx, prob, G.extract_params(N, 50, precision=precision, init_mode=1, collect=0, form=form), state=st2)
     assert torch.equal(st1["z"], st2["z"]) and torch.equal(st1["m"], st2["m"])
-    big = G.extract_params(N, 80, precision=precision, init_mode=1, pool_capacity=1 << 20)
+    big = G.extract_params(N, 80, precision=precision, init_mode=1, pool_capacity=1 << 20, form=form)
     kb, sb = G.extract(ctx, prob, big, state={"z": _dev(z0)})
     cap = kb.shape[0]           # every distinct key fits; the events do not
     assert sb["inbox_events"] > cap
-    ks, _ = G.extract(ctx, prob, G.extract_params(N, 80, precision=precision, init_mode=1, pool_capacity=cap),
-                      state={"z": _dev(z0)})
+    ks, _ = G.extract(ctx, prob, G.extract_params(N, 80, precision=precision, init_mode=1, pool_capacity=cap,
+                                                  form=form), state={"z": _dev(z0)})
     assert torch.equal(kb, ks)
-    _say("wide resume / replay", prec, "unique", kb.shape[0], "events", sb["inbox_events"])
+    _say("wide resume / replay", prec, "unique", kb.shape[0], "events", sb["inbox_events"], "row entries",
+         sb["row_entries"])
+    assert (sb["row_entries"] > 0) == (prec == "fp32")
 
 
 def test_quartic_precision_forms_equal_recall(G, ctx):
