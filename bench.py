@@ -32,11 +32,33 @@ sys.path.insert(0, ROOT)
 PEAK_FP32_MFMA = 157.3  # TFLOP/s, MI355X dense FP32 matrix
 PEAK_BF16_MFMA = 2500.0  # TFLOP/s, MI355X dense bf16 matrix
 PEAK_HBM = 8000.0       # GB/s
+PEAK_FP32_VALU = 157.3  # TFLOP/s, MI355X fp32 vector (256 CUs x 4 SIMDs x 2.4 GHz, packed FMA)
 
 
 def _big_kernel_name(stats, form):
-    """The large-basis descent kernel an extraction ran, from its tile."""
+    """The large-basis descent kernel an extraction ran, from its tile (or
+    the sparse-form kernel, templated on the 64-coordinate slots per lane)."""
+    if stats.get("row_entries", 0) > 0:
+        return f"k_descent_sparse<{_sparse_dc(stats['d'])}>" if "d" in stats else "k_descent_sparse"
     return f"k_descent_big<{stats.get('tile_slices', 0)},{stats.get('tile_blocks', 0)},{form}>"
+
+
+def _sparse_dc(d):
+    """Coordinate slots of 64 per lane of the sparse-form kernel instance for d."""
+    return next(c for c in (2, 4, 6, 8, 12, 16) if 64 * c >= d)
+
+
+def sparse_roofline(nnz, d, N, T, ms):
+    """Roofline of one sparse-form descent launch (ALU bound).  Algorithmic
+    work per start-iteration: 2 flop per nonzero of B for the forward B z, 1
+    (a signed integer add) per nonzero for the backward B^T sign(B z), and 20
+    per coordinate for the integrality and barrier terms and Adam (term 7,
+    first moment 3, second moment 4, step 6); priced at the fp32 vector peak."""
+    ops = (3.0 * nnz + 20.0 * d) * N * T
+    t = ms * 1e-3
+    return {"achieved": ops / t / 1e12, "peak": PEAK_FP32_VALU, "frac": ops / t / 1e12 / PEAK_FP32_VALU,
+            "algorithmic": "3*nnz(B) + 20*d flop per start-iteration (forward multiply-adds, backward signed adds, "
+                           "Adam and the integrality term per coordinate)"}
 
 
 def descent_roofline(n, d, N, T, ms, bf16_iters=0):
@@ -67,6 +89,9 @@ KERNEL_SOURCES = ["paper_2412_13576_amd/csrc/descent_f32.hip", "paper_2412_13576
                   "paper_2412_13576_amd/csrc/pool_device.h"]
 TRAFFIC_PROFILE_BIG = os.path.join(ROOT, "profiles", "k_descent_big_quartic_m50_n400_hbm_traffic.md")
 KERNEL_SOURCES_BIG = ["paper_2412_13576_amd/csrc/descent_big.hip", "paper_2412_13576_amd/csrc/graver_internal.h"]
+TRAFFIC_PROFILE_SPARSE = os.path.join(ROOT, "profiles", "k_descent_sparse_quartic_m50_n400_hbm_traffic.md")
+KERNEL_SOURCES_SPARSE = ["paper_2412_13576_amd/csrc/descent_sparse.hip", "paper_2412_13576_amd/csrc/descent_sparse.h",
+                         "paper_2412_13576_amd/csrc/graver_internal.h"]
 
 
 def kernel_sources_sha256(sources=None) -> str:
@@ -204,9 +229,12 @@ def bench_precision(args):
     res = {}
     for prec in ("fp32", "bf16"):
         pv = G.GRAVER_FP32 if prec == "fp32" else G.GRAVER_BF16
+        # (both forms on matrix cores: the comparison is between the binary32
+        # and the bf16 contractions)
+        fm = G.GRAVER_FORM_DENSE
         prm = G.extract_params(N, T, precision=pv, init_mode=0, seed=3, polish_iters=T // 10 if prec == "bf16" else 0,
-                               collect=0)
-        G.extract(ctx, prob, G.extract_params(4096, 8, precision=pv, init_mode=0, seed=1, collect=0))
+                               collect=0, form=fm)
+        G.extract(ctx, prob, G.extract_params(4096, 8, precision=pv, init_mode=0, seed=1, collect=0, form=fm))
         torch.cuda.synchronize()
         t = time.perf_counter()
         _, st = G.extract(ctx, prob, prm)
@@ -222,7 +250,8 @@ def bench_precision(args):
     for prec in ("fp32", "bf16"):
         pv = G.GRAVER_FP32 if prec == "fp32" else G.GRAVER_BF16
         k, st = G.extract(ctx, prob, G.extract_params(Nr, T, precision=pv, init_mode=0, seed=3, pool_capacity=1 << 25,
-                                                      polish_iters=T // 10 if prec == "bf16" else 0))
+                                                      polish_iters=T // 10 if prec == "bf16" else 0,
+                                                      form=G.GRAVER_FORM_DENSE))
         F[prec] = G.filter_minimal(ctx, k)
         res[prec]["unique_at_recall_size"] = int(k.shape[0])
         del k
@@ -239,7 +268,8 @@ def bench_precision(args):
     _line("start-iterations/s of the descent, bf16 vs binary32 (extraction, precision comparison)",
           res["bf16"]["start_iterations_per_s"], "start-iterations/s", 1, 1, res["bf16"]["wall_ms"], "bf16+f32",
           {"workload": "quartic_m50_n400: m=50, n=400 (d=350), 4 nonzeros per row in +-1..+-5, separable "
-                       "quartic f, box [-20,20]", "starts": N, "iters": T, "recall_starts": Nr},
+                       "quartic f, box [-20,20]", "starts": N, "iters": T, "recall_starts": Nr,
+           "forms": "both on matrix cores (the binary32 default on this basis is the sparse form)"},
           precision=res, speedup_bf16_over_fp32=res["fp32"]["wall_ms"] / res["bf16"]["wall_ms"],
           roofline={"bound": "mfma", "kernel": res["fp32"]["kernel"], "achieved": roof32["achieved"],
                     "peak": roof32["peak"], "unit": "TFLOP/s", "frac": roof32["frac"], "traffic": None,
@@ -510,7 +540,28 @@ def bench_quartic(args):
     el = time.perf_counter() - t0
     ms_step = el * 1000.0 / args.steps
     desc_ms = float(np.mean([r["stats"]["ms_descent"] for r in recs]))
-    roof = descent_roofline(n, d, N, T, desc_ms)
+    nnz = int(np.count_nonzero(B))
+    st_last = dict(recs[-1]["stats"], d=d)
+    sparse_form = st_last["row_entries"] > 0
+    if sparse_form:
+        roof = sparse_roofline(nnz, d, N, T, desc_ms)
+        roofline = {"bound": "alu", "kernel": _big_kernel_name(st_last, "fp32"), "achieved": roof["achieved"],
+                    "peak": roof["peak"], "unit": "TFLOP/s", "frac": roof["frac"],
+                    "traffic": _measured_traffic(N, T, "fp32", TRAFFIC_PROFILE_SPARSE, KERNEL_SOURCES_SPARSE),
+                    "algorithmic": roof["algorithmic"],
+                    "peak_note": "fp32 vector peak; the kernel's limits are LDS and VALU instruction issue (gathers "
+                                 "and integer scatter-adds over B's row lists), one start per wavefront",
+                    "note": f"sparse form: B has {nnz} nonzeros of {n * d} ({st_last['row_entries']} row-list "
+                            "entries per lane); the matrix-core kernel on the same launch is in dense_form"}
+    else:
+        roof = descent_roofline(n, d, N, T, desc_ms)
+        roofline = {"bound": "mfma", "kernel": _big_kernel_name(st_last, "fp32"), "achieved": roof["achieved"],
+                    "peak": roof["peak"], "unit": "TFLOP/s", "frac": roof["frac"],
+                    "traffic": _measured_traffic(N, T, "fp32", TRAFFIC_PROFILE_BIG, KERNEL_SOURCES_BIG),
+                    "algorithmic": "4*n*d flop per start-iteration (B z forward + B^T sign backward)",
+                    "peak_note": roof["peak_note"],
+                    "note": "algorithmic work is counted dense; the binary32 kernel skips the products of the zero "
+                            f"16x16 blocks of B ({nzb} of {nb_total} blocks are nonzero here)"}
     mean = lambda key: float(np.mean([r[key] for r in recs]))
     out = {
         "metric": "start-iterations/s (whole path: extraction + filter + augmentation)",
@@ -527,7 +578,8 @@ def bench_quartic(args):
         "data": "synthetic",
         "config": {"workload": "quartic_m50_n400: m=50, n=400 (d=350), A with 4 nonzeros per row in +-1..+-5, "
                                "separable degree-4 f, box [-20,20] (the precision configuration's instance, binary32 "
-                               "form)", "starts": N, "iters": T, "aug_starts": S0, "precision": "fp32-mfma"},
+                               "form)", "starts": N, "iters": T, "aug_starts": S0,
+                   "precision": "fp32-sparse" if sparse_form else "fp32-mfma"},
         "verified_directions_per_s": mean("unique") / (ms_step * 1e-3),
         "verified_directions_per_s_extraction": mean("unique") / mean("t_extract"),
         "descent_start_iterations_per_s": N * T / (desc_ms * 1e-3),
@@ -538,14 +590,26 @@ def bench_quartic(args):
         "filtered": mean("filtered"),
         "aug_best_f": recs[-1]["best_f"],
         "aug_mean_steps": recs[-1]["mean_steps"],
-        "roofline": {"bound": "mfma", "kernel": _big_kernel_name(recs[-1]["stats"], "fp32"), "achieved": roof["achieved"],
-                     "peak": roof["peak"], "unit": "TFLOP/s", "frac": roof["frac"],
-                     "traffic": _measured_traffic(N, T, "fp32", TRAFFIC_PROFILE_BIG, KERNEL_SOURCES_BIG),
-                     "algorithmic": "4*n*d flop per start-iteration (B z forward + B^T sign backward)",
-                     "peak_note": roof["peak_note"],
-                     "note": "algorithmic work is counted dense; the binary32 kernel skips the products of the zero "
-                             f"16x16 blocks of B ({nzb} of {nb_total} blocks are nonzero here)"},
+        "roofline": roofline,
     }
+    if sparse_form and not args.no_dense_leg:
+        # the binary32 matrix-core kernel on the same launch (extraction only)
+        torch.cuda.synchronize()
+        prm = G.extract_params(N, T, precision=G.GRAVER_FP32, init_mode=0, seed=2000, pool_capacity=pool_cap,
+                               any_order=True, form=G.GRAVER_FORM_DENSE)
+        kd, sd = G.extract(ctx, prob, prm)
+        del kd
+        torch.cuda.synchronize()
+        rd = descent_roofline(n, d, N, T, sd["ms_descent"])
+        out["dense_form"] = {
+            "kernel": _big_kernel_name(dict(sd, d=d), "fp32"), "descent_ms": sd["ms_descent"],
+            "unique": sd["unique"], "sparse_speedup": sd["ms_descent"] / desc_ms,
+            "roofline": {"bound": "mfma", "achieved": rd["achieved"], "peak": rd["peak"], "frac": rd["frac"],
+                         "unit": "TFLOP/s", "algorithmic": "4*n*d flop per start-iteration",
+                         "traffic": _measured_traffic(N, T, "fp32", TRAFFIC_PROFILE_BIG, KERNEL_SOURCES_BIG),
+                         "note": f"dense count; the kernel skips the zero 16x16 blocks of B ({nzb} of {nb_total} "
+                                 "are nonzero)"}}
+        print(f"[quartic] dense-form descent {sd['ms_descent']:.0f} ms", file=sys.stderr, flush=True)
     if not args.no_bf16_line:
         torch.cuda.synchronize()
         tb = time.perf_counter()
@@ -558,6 +622,8 @@ def bench_quartic(args):
             "descent_ms": rb["stats"]["ms_descent"], "unique": rb["unique"], "filtered": rb["filtered"],
             "stage_s": {"extract": rb["t_extract"], "filter": rb["t_filter"], "augment": rb["t_augment"]},
             "speedup_descent_over_fp32": desc_ms / rb["stats"]["ms_descent"],
+            "speedup_descent_over_fp32_matrix_cores": (out["dense_form"]["descent_ms"] / rb["stats"]["ms_descent"]
+                                                       if "dense_form" in out else desc_ms / rb["stats"]["ms_descent"]),
             "roofline": {"achieved": rfb["achieved"], "peak": rfb["peak"], "frac": rfb["frac"], "unit": "TFLOP/s"},
             "form": "forward on bf16 matrix cores with z split exactly into three bf16 parts, fp32 accumulation; "
                     f"last {T // 10} iterations binary32"}
@@ -681,6 +747,8 @@ def main():
     ap.add_argument("--serve-leg", type=int, default=60,
                     help="quartic: requests of the short serving leg reported beside (0: none)")
     ap.add_argument("--no-bf16-line", action="store_true", help="quartic: skip the bf16 + polish step")
+    ap.add_argument("--no-dense-leg", action="store_true",
+                    help="quartic: skip the matrix-core extraction of the same launch")
     ap.add_argument("--requests", type=int, default=300, help="serve: number of requests")
     ap.add_argument("--n-max", type=int, default=1000, help="serve: largest n of the request law")
     ap.add_argument("--copy-calibration", action="store_true",

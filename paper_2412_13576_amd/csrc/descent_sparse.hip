@@ -34,7 +34,7 @@ namespace graver {
 namespace {
 
 constexpr int kSpWaves = 4;       // starts (wavefronts) per block
-constexpr int kSpLogChunk = 16;   // log rows reserved by a wave at a time
+constexpr int kSpLogChunk = 16;   // log rows reserved by a wave at a time (at most)
 constexpr int kSpMaxSlots = 16;   // n <= 1024
 constexpr int kSpMaxEntries = 128;  // row-list entries per lane (32 KB of LDS)
 
@@ -46,6 +46,7 @@ struct SparseArgs {
   const uint32_t* row;  // nc x 64 row words
   uint32_t slot[kSpMaxSlots];  // width | first entry << 16
   int nc, ew, DB, stride;
+  uint32_t chunk;  // log rows a wave reserves at a time
   float* state;  // z, then m, then v, `per` floats each (wave-native layout)
   int64_t per;
   unsigned long long* counters;
@@ -198,12 +199,12 @@ __global__ __launch_bounds__(64 * kSpWaves, (sp_waves_per_simd<DC>())) void k_de
             ++n_inbox;
             if (lleft == 0 && !log_full) {
               uint32_t nb = 0;
-              if (lane == 0) nb = atomicAdd(log.count, (uint32_t)kSpLogChunk);
+              if (lane == 0) nb = atomicAdd(log.count, g.chunk);
               nb = __builtin_amdgcn_readfirstlane(nb);
               if (nb < log.cap) {
                 lbase = nb;
                 lused = 0;
-                lleft = (int)(min(log.cap, nb + (uint32_t)kSpLogChunk) - nb);
+                lleft = (int)(min(log.cap, nb + g.chunk) - nb);
               }
             }
             if (lleft == 0) {
@@ -383,6 +384,11 @@ hipError_t launch_descent_sparse(hipStream_t s, const DescentArgs& a, const Spar
   g.per = per;
   g.counters = counters;
   g.rlim = rlim;
+  // A wave leaves up to chunk - 1 reserved rows unused, so the reservation
+  // shrinks with the log's capacity per start: the unused rows of one launch
+  // stay within a quarter of the log (a small log then still holds the
+  // candidates of one iteration whenever it holds one row per start).
+  g.chunk = (uint32_t)std::min<int64_t>(kSpLogChunk, std::max<int64_t>(1, (int64_t)a.log.cap / (4 * a.N)));
   if (g.stride % 16 != 0 || g.stride < a.n) return hipErrorInvalidValue;
   const size_t shmem = (size_t)(img.nc + img.ew) * 64 * 4 + (size_t)kSpWaves * 2 * 64 * dc * 4 +
                        (size_t)kSpWaves * g.stride;

@@ -50,11 +50,15 @@ def _batch(G):
     return _cache["b"]
 
 
-def _params(G, item, T=60, cap=None):
+def _params(G, item, T=60, cap=None, form=None):
+    """Matrix-core forms by default (the shared grids and their tile shapes
+    are what these tests cover); form=GRAVER_FORM_AUTO lets the binary32
+    instances, whose bases are sparse, take the sparse form (run alone)."""
     inst, B, z0, prec, pol, pcap = item
     p = G.GRAVER_FP32 if prec == "fp32" else G.GRAVER_BF16
     return G.extract_params(z0.shape[0], T, precision=p, init_mode=1, polish_iters=pol,
-                            pool_capacity=pcap if cap is None else cap)
+                            pool_capacity=pcap if cap is None else cap,
+                            form=G.GRAVER_FORM_DENSE if form is None else form)
 
 
 def _state(item):
@@ -89,6 +93,30 @@ def test_batch_equals_single_calls(G, graph):
         assert s1["inbox_events"] == stats[i]["inbox_events"]
         K = keys[i].cpu().numpy().astype(np.int64)
         assert K.shape[0] > 0 and np.all(K @ it[0].A.T == 0)
+    ctx.close()
+    single.close()
+
+
+def test_batch_with_sparse_form_instances_equals_single_calls(G):
+    """The binary32 instances take the sparse form (alone, outside the shared
+    grids) next to the bf16 instances' shared grids: every instance's keys,
+    final state and event count equal a single call's."""
+    items = _batch(G)
+    ctx = G.Context(0)
+    auto = G.GRAVER_FORM_AUTO
+    probs = [G.DeviceProblem.from_numpy(it[0].A, it[0].b, it[0].l, it[0].u, it[1]) for it in items]
+    prms = [_params(G, it, form=auto) for it in items]
+    states = [_state(it) for it in items]
+    keys, stats, bs = G.extract_batch(ctx, probs, prms, states, use_graph=True)
+    _say("batch sparse", bs, [s["row_entries"] for s in stats])
+    assert sum(s["row_entries"] > 0 for s in stats) >= 2
+    single = G.Context(0)
+    for i, it in enumerate(items):
+        st = _state(it)
+        k1, s1 = G.extract(single, probs[i], _params(G, it, form=auto), state=st)
+        assert torch.equal(keys[i], k1)
+        assert torch.equal(states[i]["z"], st["z"]) and torch.equal(states[i]["m"], st["m"])
+        assert s1["inbox_events"] == stats[i]["inbox_events"]
     ctx.close()
     single.close()
 
