@@ -243,16 +243,37 @@ __global__ void k_eval(AugArgs a, const int64_t* X, const uint32_t* done, const 
             }
           }
         } else {
+          // the support of g in ascending order, gathered once for every
+          // step length (the sums below run over it in the same order as a
+          // scan of all n coordinates that skips zeros); a support longer
+          // than kSupp is scanned in full
+          constexpr int kSupp = 32;
+          int sidx[kSupp];
+          int ns = 0;
+          for (int i = 0; i < n && ns <= kSupp; ++i)
+            if (g[i] != 0) {
+              if (ns < kSupp) sidx[ns] = i;
+              ++ns;
+            }
+          const bool compact = ns <= kSupp;
           for (int sg = 0; sg < 2; ++sg) {
             const int64_t lm = sg ? ln : lp;
             const int sgn = sg ? -1 : 1;
             for (int64_t lam = 1; lam <= lm; ++lam) {
               double acc = 0.0;
-              for (int i = 0; i < n; ++i) {
-                const int gi = g[i];
-                if (gi == 0) continue;
-                const int64_t v = x[i] + lam * sgn * gi;
-                acc = acc + (tab[(size_t)i * w + (v - a.l[i])] - r[i]);
+              if (compact) {
+                for (int t = 0; t < ns; ++t) {
+                  const int i = sidx[t];
+                  const int64_t v = x[i] + lam * sgn * g[i];
+                  acc = acc + (tab[(size_t)i * w + (v - a.l[i])] - r[i]);
+                }
+              } else {
+                for (int i = 0; i < n; ++i) {
+                  const int gi = g[i];
+                  if (gi == 0) continue;
+                  const int64_t v = x[i] + lam * sgn * gi;
+                  acc = acc + (tab[(size_t)i * w + (v - a.l[i])] - r[i]);
+                }
               }
               Move mv{acc, (uint32_t)(2 * k + sg), (int32_t)lam};
               if (better(mv, best)) best = mv;
