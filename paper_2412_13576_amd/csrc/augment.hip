@@ -247,7 +247,7 @@ __global__ void k_eval(AugArgs a, const int64_t* X, const uint32_t* done, const 
           // step length (the sums below run over it in the same order as a
           // scan of all n coordinates that skips zeros); a support longer
           // than kSupp is scanned in full
-          constexpr int kSupp = 32;
+          constexpr int kSupp = 8;
           int sidx[kSupp];
           int ns = 0;
           for (int i = 0; i < n && ns <= kSupp; ++i)
